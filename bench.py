@@ -1,0 +1,163 @@
+#!/usr/bin/env python3
+"""Benchmark of the ghost-penalty apply y = G(gamma) u on one MI355X.
+
+Default workload: 3D Q5 on GLL nodes, 128^3 cells of [-1,1]^3 cut by a ball of
+radius 0.73 (122,353 ghost faces, 396 patch DoFs per face), u ~ U[-1,1] from
+seed 1, gamma_j = 0.5 h^{2j-1}/(j!)^2.  One step = one FP64 accumulating apply
+(gather, normal contraction, tangential masses, expansion, scatter) over every
+ghost face.  The FP32 apply is timed the same way and reported with its
+normwise error against the FP64 result.
+
+Prints ONE JSON line.  Metric: ghost-face patch DoFs per second,
+faces * (2k+1)(k+1)^{d-1} / t / 1e9.  The roofline object refers to the face
+kernel: compulsory HBM bytes per launch (24 B per support DoF in FP64: read u,
+read and write y) over its average launch time, measured with HIP events on
+the stream the kernel runs on.
+"""
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="ball3d_q5_128")
+    ap.add_argument("--coloured", action="store_true", help="race-free colour scatter instead of atomics")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="one JSON line per degree/mesh of the roofline sweep")
+    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
+    return ap.parse_args()
+
+
+def timed_applies(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / 1e3 / steps  # seconds per step
+
+
+def cpu_baseline(w, u_np):
+    """The oracle's apply on the same workload, timed on the host cores (assembly excluded)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle.operator import GhostOracle
+    o = GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), centre=w.centre, radius=w.radius)
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    t0 = time.perf_counter()
+    o.apply(u_np)
+    dt = time.perf_counter() - t0
+    faces = o.n_faces()
+    return {"value": round(faces * w.n_p / dt / 1e9, 6), "unit": "GDoF/s", "cores": threads, "kind": "oracle",
+            "sample": f"one full oracle apply of {w.name} ({faces} faces, dense per-face patch matvec "
+                      f"by BLAS + scatter-add), {dt:.1f} s, host {platform.processor() or platform.machine()}, "
+                      f"{os.cpu_count()} logical CPUs"}
+
+
+def run_workload(w, args, with_cpu):
+    import numpy as np
+    import torch
+    from paper_2503_00246_amd.operator import GhostOperator
+    from paper_2503_00246_amd.workloads import SEED_U, uniform_vector
+
+    op = GhostOperator.from_workload(w, coloured=args.coloured)
+    st = op.stats
+    u_np = uniform_vector(w.n_lattice, SEED_U)
+    u = torch.from_numpy(u_np).cuda()
+    y = torch.zeros_like(u)
+    t64 = timed_applies(lambda: op.apply(u, y, accumulate=True), args.steps, args.warmup)
+    patch_dofs = st["n_faces_total"] * st["n_patch_dofs"]
+    out = {"t64": t64, "gdofs64": patch_dofs / t64 / 1e9, "stats": st}
+    if not args.no_fp32:
+        u32 = u.float()
+        y32 = torch.zeros_like(u32)
+        t32 = timed_applies(lambda: op.apply_f32(u32, y32, accumulate=True), args.steps, args.warmup)
+        ref = op.apply(u)
+        got = op.apply_f32(u32).double()
+        err = float((got - ref).abs().max() / ref.abs().max())
+        out.update(t32=t32, gdofs32=patch_dofs / t32 / 1e9, err32=err)
+    if with_cpu:
+        out["cpu"] = cpu_baseline(w, u_np)
+    del u, y
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is a "
+              f"design note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2503_00246_amd.workloads import WORKLOADS, sweep_workload
+
+    if args.sweep:
+        for k, n in [(3, 128), (3, 96), (4, 96), (5, 96), (5, 128), (6, 96), (7, 96)]:
+            w = sweep_workload(k, n)
+            r = run_workload(w, args, with_cpu=False)
+            st = r["stats"]
+            print(json.dumps({"workload": w.name, "faces": st["n_faces_total"], "n_p": st["n_patch_dofs"],
+                              "ms64": r["t64"] * 1e3, "gdofs64": r["gdofs64"],
+                              "frac64": st["bytes_fp64"] / r["t64"] / 1e9 / HBM_PEAK_GBS,
+                              "ms32": r.get("t32", 0) * 1e3, "gdofs32": r.get("gdofs32"),
+                              "frac32": st["bytes_fp32"] / r["t32"] / 1e9 / HBM_PEAK_GBS if "t32" in r else None,
+                              "err32": r.get("err32")}), flush=True)
+        return
+
+    w = WORKLOADS[args.workload]
+    r = run_workload(w, args, with_cpu=not args.no_cpu)
+    st = r["stats"]
+    achieved = st["bytes_fp64"] / r["t64"] / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            traffic = json.load(f).get(w.name)
+    line = {
+        "metric": "ghost-face patch DoFs/s for G.u (GDoF/s), FP64 vs FP32 at stated error, d=3",
+        "value": round(r["gdofs64"], 4),
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["t64"] * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "d": w.d, "k": w.k, "cells_per_axis": w.n[0],
+                   "faces": st["n_faces_total"], "patch_dofs_per_face": st["n_patch_dofs"],
+                   "support_dofs": st["n_support_dofs"], "lattice_dofs": st["n_lattice"],
+                   "scatter": "colour" if args.coloured else "atomic", "mode": "accumulate"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "fp32": None if "t32" not in r else {
+            "value": round(r["gdofs32"], 4), "unit": "GDoF/s", "ms_per_step": round(r["t32"] * 1e3, 5),
+            "normwise_err_vs_fp64": r["err32"],
+            "roofline_frac": round(st["bytes_fp32"] / r["t32"] / 1e9 / HBM_PEAK_GBS, 4)},
+        "cpu_baseline": r.get("cpu"),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

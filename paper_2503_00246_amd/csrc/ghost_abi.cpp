@@ -1,0 +1,393 @@
+// C ABI of libghost: argument checking, context ownership, uploads, error reporting.
+// No C++ exception crosses this file's extern "C" functions.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ghost.h"
+#include "ghost_device.h"
+#include "ghost_plan.h"
+#include "ghost_cg.h"
+
+struct ghost_ctx {
+  ghost::Plan plan;
+  ghost::DevPlan dev;
+  int device = -1;
+  std::vector<double> gamma;
+  std::vector<void *> allocs;         // device allocations owned by the context
+  ghost::CgWork *cg = nullptr;        // lazily allocated CG workspace
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char *what) {
+  return fail(GHOST_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Makes ctx's device current for the duration of a call and restores the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err != hipSuccess) { ok = false; return; }
+    if (prev != dev) {
+      err = hipSetDevice(dev);
+      ok = err == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (ok && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+int upload(ghost_ctx *c, const T *src, size_t n, T **dst) {
+  *dst = nullptr;
+  if (n == 0) return GHOST_OK;
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GHOST_ENOMEM, "hipMalloc of %zu bytes failed: %s", n * sizeof(T), hipGetErrorString(e));
+  }
+  c->allocs.push_back(p);
+  if (src) {
+    e = hipMemcpy(p, src, n * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpy");
+  }
+  *dst = static_cast<T *>(p);
+  return GHOST_OK;
+}
+
+void free_device(ghost_ctx *c) {
+  if (c->device < 0) return;
+  DeviceGuard g(c->device);
+  if (c->cg) ghost::cg_free(c->cg);
+  c->cg = nullptr;
+  for (void *p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+}
+
+bool finite_nonneg(const double *g, int k) {
+  for (int j = 0; j < k; ++j)
+    if (!std::isfinite(g[j]) || g[j] < 0) return false;
+  return true;
+}
+
+// Host copy of both table buffers for the current gamma.
+void host_tables(const ghost_ctx *c, std::vector<double> &t64, std::vector<float> &t32) {
+  const ghost::Plan &p = c->plan;
+  const int k = p.k, NN = 2 * k + 1, K = k + 1;
+  t64.assign(ghost::tab_size64(k), 0.0);
+  t32.assign(ghost::tab_size32(k), 0.0f);
+  for (int j = 0; j < k; ++j) {
+    const long double hs = powl((long double)p.h, (long double)(p.dim - 1 - 2 * (j + 1)));
+    t64[ghost::tab_hscale(k) + j] = (double)hs;
+  }
+  for (int i = 0; i < k * NN; ++i) {
+    const int j = i / NN;
+    t64[i] = p.jumps[i];
+    t64[ghost::tab_gs(k) + i] = (c->gamma[j] * t64[ghost::tab_hscale(k) + j]) * p.jumps[i];
+  }
+  for (int i = 0; i < K * K; ++i) t64[ghost::tab_M(k) + i] = p.mass[i];
+  for (int i = 0; i < K; ++i) t64[ghost::tab_gllw(k) + i] = p.weights[i];
+  for (int i = 0; i < ghost::tab_size32(k); ++i) t32[i] = (float)t64[i];
+}
+
+int check_apply(const ghost_ctx *ctx, const void *u, const void *y, size_t elem) {
+  if (!ctx) return fail(GHOST_EINVAL, "null context");
+  if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context (device = -1) cannot apply");
+  if (!u || !y) return fail(GHOST_EINVAL, "null vector pointer");
+  const char *a = static_cast<const char *>(u), *b = static_cast<const char *>(y);
+  const size_t bytes = (size_t)ctx->plan.n_lattice * elem;
+  if ((a <= b && b < a + bytes) || (b <= a && a < b + bytes))
+    return fail(GHOST_EINVAL, "input and output vectors overlap");
+  return GHOST_OK;
+}
+
+}  // namespace
+
+namespace ghost {
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+const DevPlan &dev_plan(const ghost_ctx *c) { return c->dev; }
+const Plan &host_plan(const ghost_ctx *c) { return c->plan; }
+CgWork *&cg_slot(ghost_ctx *c) { return c->cg; }
+int ctx_device(const ghost_ctx *c) { return c->device; }
+}  // namespace ghost
+
+extern "C" {
+
+const char *ghost_last_error(void) { return g_error.c_str(); }
+
+int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const double *gamma, unsigned flags,
+                int device, ghost_ctx **out) {
+  g_error.clear();
+  if (!out) return fail(GHOST_EINVAL, "out is null");
+  *out = nullptr;
+  if (!mesh || !ls || !gamma) return fail(GHOST_EINVAL, "null mesh, level set or gamma");
+  if (mesh->dim != 2 && mesh->dim != 3) return fail(GHOST_EINVAL, "dim must be 2 or 3 (got %d)", mesh->dim);
+  if (k < 1 || k > GHOST_KMAX) return fail(GHOST_EINVAL, "k must be in 1..%d (got %d)", GHOST_KMAX, k);
+  for (int a = 0; a < mesh->dim; ++a) {
+    if (mesh->n[a] < 2) return fail(GHOST_EINVAL, "n[%d] must be >= 2", a);
+    if (mesh->n[a] > (1 << 20)) return fail(GHOST_EINVAL, "n[%d] too large", a);
+    if (!std::isfinite(mesh->lo[a])) return fail(GHOST_EINVAL, "lo must be finite");
+  }
+  if (!(mesh->h > 0) || !std::isfinite(mesh->h)) return fail(GHOST_EINVAL, "h must be positive and finite");
+  if (!finite_nonneg(gamma, k)) return fail(GHOST_EINVAL, "gamma must be finite and >= 0");
+  if (ls->kind == GHOST_LS_BALL) {
+    if (!(ls->radius > 0) || !std::isfinite(ls->radius)) return fail(GHOST_EINVAL, "radius must be positive");
+    for (int a = 0; a < mesh->dim; ++a)
+      if (!std::isfinite(ls->centre[a])) return fail(GHOST_EINVAL, "centre must be finite");
+  } else if (ls->kind == GHOST_LS_CELLS) {
+    if (!ls->cell_class) return fail(GHOST_EINVAL, "cell_class is null");
+  } else {
+    return fail(GHOST_EINVAL, "unknown level-set kind %d", ls->kind);
+  }
+  if (flags & ~(GHOST_FP64 | GHOST_FP32 | GHOST_COLOURED)) return fail(GHOST_EINVAL, "unknown flags");
+  if (device < -1) return fail(GHOST_EINVAL, "device must be >= -1");
+
+  ghost_ctx *c = new (std::nothrow) ghost_ctx;
+  if (!c) return fail(GHOST_ENOMEM, "out of host memory");
+  try {
+    c->gamma.assign(gamma, gamma + k);
+    std::string err = ghost::build_plan(c->plan, mesh->dim, mesh->n, mesh->lo, mesh->h, k, ls->kind,
+                                        ls->centre, ls->radius, ls->cell_class, (flags & GHOST_COLOURED) != 0);
+    if (!err.empty()) {
+      delete c;
+      return fail(GHOST_EINVAL, "%s", err.c_str());
+    }
+  } catch (const std::bad_alloc &) {
+    delete c;
+    return fail(GHOST_ENOMEM, "out of host memory building the plan");
+  } catch (...) {
+    delete c;
+    return fail(GHOST_EINVAL, "plan construction failed");
+  }
+
+  const ghost::Plan &p = c->plan;
+  ghost::DevPlan &d = c->dev;
+  d.dim = p.dim;
+  d.k = p.k;
+  d.h = p.h;
+  for (int a = 0; a < 3; ++a) {
+    d.stride[a] = (int32_t)p.stride[a];
+    d.n[a] = p.n[a];
+    d.L[a] = p.L[a];
+  }
+  d.n_batches = (int)p.batches.size();
+  d.coloured = p.coloured;
+  d.n_colours = p.n_colours;
+  d.colour_begin = p.colour_begin.empty() ? nullptr : p.colour_begin.data();
+  d.n_support_runs = (int)p.support_runs.size();
+  d.n_active_runs = (int)p.active_runs.size();
+
+  if (device >= 0) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || device >= count) {
+      delete c;
+      return e != hipSuccess ? fail_hip(e, "hipGetDeviceCount")
+                             : fail(GHOST_EINVAL, "device %d not present (%d devices)", device, count);
+    }
+    c->device = device;
+    DeviceGuard g(device);
+    if (!g.ok) {
+      c->device = -1;
+      delete c;
+      return fail_hip(g.err, "hipSetDevice");
+    }
+    std::vector<double> t64;
+    std::vector<float> t32;
+    host_tables(c, t64, t32);
+    int rc = GHOST_OK;
+    const int64_t *fb = nullptr;
+    const ghost::Batch *bt = nullptr;
+    const ghost::Run *sr = nullptr, *ar = nullptr;
+    const int8_t *cl = nullptr;
+    if (rc == GHOST_OK) rc = upload(c, p.face_base.data(), p.face_base.size(), const_cast<int64_t **>(&fb));
+    if (rc == GHOST_OK) rc = upload(c, p.batches.data(), p.batches.size(), const_cast<ghost::Batch **>(&bt));
+    if (rc == GHOST_OK) rc = upload(c, p.support_runs.data(), p.support_runs.size(), const_cast<ghost::Run **>(&sr));
+    if (rc == GHOST_OK) rc = upload(c, p.active_runs.data(), p.active_runs.size(), const_cast<ghost::Run **>(&ar));
+    if (rc == GHOST_OK) rc = upload(c, p.cls.data(), p.cls.size(), const_cast<int8_t **>(&cl));
+    if (rc == GHOST_OK) rc = upload(c, t64.data(), t64.size(), &d.tab64);
+    if (rc == GHOST_OK) rc = upload(c, t32.data(), t32.size(), &d.tab32);
+    if (rc == GHOST_OK) rc = upload<double>(c, nullptr, (size_t)std::max(1, d.n_batches) * k, &d.vjp_partial);
+    if (rc != GHOST_OK) {
+      std::string msg = g_error;
+      free_device(c);
+      delete c;
+      g_error = msg;
+      return rc;
+    }
+    d.face_base = fb;
+    d.batches = bt;
+    d.support_runs = sr;
+    d.active_runs = ar;
+    d.cls = cl;
+  }
+  *out = c;
+  return GHOST_OK;
+}
+
+void ghost_destroy(ghost_ctx *ctx) {
+  if (!ctx) return;
+  free_device(ctx);
+  delete ctx;
+}
+
+int ghost_set_gamma(ghost_ctx *ctx, const double *gamma, int gamma_on_device, void *stream) {
+  if (!ctx || !gamma) return fail(GHOST_EINVAL, "null context or gamma");
+  if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  hipError_t e;
+  if (gamma_on_device) {
+    e = ghost::launch_set_gamma(ctx->dev, gamma, static_cast<hipStream_t>(stream));
+  } else {
+    if (!finite_nonneg(gamma, ctx->plan.k)) return fail(GHOST_EINVAL, "gamma must be finite and >= 0");
+    ctx->gamma.assign(gamma, gamma + ctx->plan.k);
+    ghost::GammaArg arg{};
+    for (int j = 0; j < ctx->plan.k; ++j) arg.v[j] = gamma[j];
+    e = ghost::launch_set_gamma_host(ctx->dev, arg, static_cast<hipStream_t>(stream));
+  }
+  return e == hipSuccess ? GHOST_OK : fail_hip(e, "set_gamma launch");
+}
+
+int ghost_apply(ghost_ctx *ctx, const double *u, double *y, int accumulate, void *stream) {
+  int rc = check_apply(ctx, u, y, sizeof(double));
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  hipError_t e = ghost::launch_apply_f64(ctx->dev, u, y, accumulate != 0, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GHOST_OK : fail_hip(e, "apply launch");
+}
+
+int ghost_apply_f32(ghost_ctx *ctx, const float *u, float *y, int accumulate, void *stream) {
+  int rc = check_apply(ctx, u, y, sizeof(float));
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  hipError_t e = ghost::launch_apply_f32(ctx->dev, u, y, accumulate != 0, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GHOST_OK : fail_hip(e, "apply_f32 launch");
+}
+
+int ghost_vjp(ghost_ctx *ctx, const double *u, const double *w, double *du, double *dgamma, int accumulate_du,
+              void *stream) {
+  int rc = check_apply(ctx, w, du, sizeof(double));
+  if (rc) return rc;
+  rc = check_apply(ctx, u, du, sizeof(double));
+  if (rc) return rc;
+  if (!dgamma) return fail(GHOST_EINVAL, "null dgamma");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  hipError_t e = ghost::launch_vjp(ctx->dev, u, w, du, dgamma, accumulate_du != 0, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GHOST_OK : fail_hip(e, "vjp launch");
+}
+
+int ghost_mass_diag(ghost_ctx *ctx, double *diag, void *stream) {
+  if (!ctx || !diag) return fail(GHOST_EINVAL, "null context or diag");
+  if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  hipError_t e = ghost::launch_mass_diag(ctx->dev, diag, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GHOST_OK : fail_hip(e, "mass_diag launch");
+}
+
+int ghost_info(const ghost_ctx *ctx, ghost_stats *out) {
+  if (!ctx || !out) return fail(GHOST_EINVAL, "null context or output");
+  const ghost::Plan &p = ctx->plan;
+  std::memset(out, 0, sizeof *out);
+  out->dim = p.dim;
+  out->k = p.k;
+  out->device = ctx->device;
+  out->n_colours = p.n_colours;
+  for (int a = 0; a < 3; ++a) {
+    out->lattice[a] = p.L[a];
+    out->n_faces[a] = (int64_t)p.face_cell[a].size() / 3;
+    out->n_faces_total += out->n_faces[a];
+  }
+  out->n_lattice = p.n_lattice;
+  out->n_cells = (int64_t)p.cls.size();
+  out->n_active_cells = p.n_active_cells;
+  out->n_cut_cells = p.n_cut_cells;
+  out->n_active_dofs = p.n_active;
+  out->n_support_dofs = p.n_support;
+  const int K = p.k + 1;
+  int64_t tang = 1;
+  for (int a = 1; a < p.dim; ++a) tang *= K;
+  out->n_patch_dofs = (2 * p.k + 1) * tang;
+  out->n_batches = (int64_t)p.batches.size();
+  out->flops_per_face = 2.0 * (2.0 * p.k * (2 * p.k + 1) * tang + (double)(p.dim - 1) * p.k * tang * K);
+  out->bytes_fp64 = 24.0 * (double)p.n_support;
+  out->bytes_fp32 = 12.0 * (double)p.n_support;
+  return GHOST_OK;
+}
+
+int ghost_faces(const ghost_ctx *ctx, int axis, int32_t *out, int64_t cap) {
+  if (!ctx || !out) return fail(GHOST_EINVAL, "null context or output");
+  if (axis < 0 || axis >= ctx->plan.dim) return fail(GHOST_EINVAL, "axis out of range");
+  const auto &fc = ctx->plan.face_cell[axis];
+  const int64_t nf = (int64_t)fc.size() / 3;
+  if (cap < nf) return fail(GHOST_EINVAL, "capacity %lld < %lld faces", (long long)cap, (long long)nf);
+  for (int64_t f = 0; f < nf; ++f) {
+    out[4 * f + 0] = fc[3 * f + 0];
+    out[4 * f + 1] = fc[3 * f + 1];
+    out[4 * f + 2] = fc[3 * f + 2];
+    out[4 * f + 3] = ctx->plan.face_colour[axis][f];
+  }
+  return GHOST_OK;
+}
+
+int ghost_tables(const ghost_ctx *ctx, double *jumps, double *mass, double *nodes, double *weights) {
+  if (!ctx) return fail(GHOST_EINVAL, "null context");
+  const ghost::Plan &p = ctx->plan;
+  if (jumps) std::memcpy(jumps, p.jumps.data(), p.jumps.size() * sizeof(double));
+  if (mass) std::memcpy(mass, p.mass.data(), p.mass.size() * sizeof(double));
+  if (nodes) std::memcpy(nodes, p.nodes.data(), p.nodes.size() * sizeof(double));
+  if (weights) std::memcpy(weights, p.weights.data(), p.weights.size() * sizeof(double));
+  return GHOST_OK;
+}
+
+int ghost_cg(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts *opts, ghost_cg_result *res,
+             void *stream) {
+  if (!ctx || !b || !x || !opts || !res) return fail(GHOST_EINVAL, "null argument");
+  if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");
+  if (b == x) return fail(GHOST_EINVAL, "b and x must differ");
+  if (opts->mode != GHOST_CG_FP64 && opts->mode != GHOST_CG_MIXED) return fail(GHOST_EINVAL, "unknown CG mode");
+  if (!(opts->tol > 0) || opts->max_iter < 1) return fail(GHOST_EINVAL, "tol must be > 0 and max_iter >= 1");
+  if (opts->mode == GHOST_CG_MIXED && !(opts->inner_tol > 0 && opts->inner_tol < 1))
+    return fail(GHOST_EINVAL, "inner_tol must be in (0, 1)");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  try {
+    return ghost::cg_solve(ctx, b, x, *opts, *res, static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc &) {
+    return fail(GHOST_ENOMEM, "out of host memory in CG");
+  } catch (...) {
+    return fail(GHOST_EINVAL, "CG failed");
+  }
+}
+
+}  // extern "C"

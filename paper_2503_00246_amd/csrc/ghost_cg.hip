@@ -1,0 +1,404 @@
+// Conjugate gradients on A x = b, A = M + G over the active lattice nodes, with all
+// vector operations in this file's kernels and every scalar (alpha, beta, residual
+// norms) kept on the device; the host reads one double per iteration for the stopping
+// test.  The paper leaves the solver open (§1, last paragraphs); this driver is the
+// linear-solve workload around the ghost-penalty apply.
+//
+// FP64 mode: plain CG from x = 0.  The recursive residual is replaced by the true one,
+// b - A x, every check_every iterations and whenever it meets the tolerance; the solve
+// stops on the true residual.
+// Mixed mode: outer refinement in FP64 (true residual r = b - A x with the FP64 apply,
+// x += e), inner CG on A e = r with FP32 vectors, FP32 ghost apply and FP32 mass, and
+// FP64 dot products and scalars, run until its residual drops by inner_tol.
+//
+// Vectors live on the lattice; kernels visit only the active nodes, cut into segments
+// of at most 256 consecutive nodes (one wavefront each, 4 nodes per lane).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "ghost_cg.h"
+
+namespace ghost {
+
+namespace {
+constexpr int kSegLen = 256;
+constexpr int kSegPerBlock = kBlockThreads / 64;
+enum { S_RR = 0, S_PQ, S_ALPHA, S_BETA, S_TMP, S_COUNT = 8 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Per-block partial of a dot product, fixed reduction order.
+__device__ __forceinline__ void block_partial(double v, double *partial) {
+  __shared__ double red[kSegPerBlock];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSegPerBlock; ++w) s += red[w];
+    partial[blockIdx.x] = s;
+  }
+}
+
+#define SEG_LOOP                                                     \
+  const int seg = blockIdx.x * kSegPerBlock + (threadIdx.x >> 6);     \
+  const int lane = threadIdx.x & 63;                                  \
+  Run sg{0, 0, 0};                                                    \
+  if (seg < n_segs) sg = segs[seg];                                   \
+  for (int i = lane; i < sg.len; i += 64)
+
+// x = 0, r = (T) src, p = r; partial <r, r>
+template <typename T>
+__global__ void start_kernel(const Run *segs, int n_segs, const double *src, T *x, T *r, T *p, double *partial) {
+  double acc = 0.0;
+  SEG_LOOP {
+    const int64_t j = sg.start + i;
+    const T v = (T)src[j];
+    x[j] = T(0);
+    r[j] = v;
+    p[j] = v;
+    acc += (double)v * (double)v;
+  }
+  block_partial(acc, partial);
+}
+
+// optionally p = r + beta p, then q = mdiag * p
+template <typename T>
+__global__ void pq_kernel(const Run *segs, int n_segs, T *p, const T *r, T *q, const T *mdiag,
+                          const double *scal, int update_p) {
+  const T beta = (T)scal[S_BETA];
+  SEG_LOOP {
+    const int64_t j = sg.start + i;
+    T pv = p[j];
+    if (update_p) {
+      pv = r[j] + beta * pv;
+      p[j] = pv;
+    }
+    q[j] = mdiag[j] * pv;
+  }
+}
+
+template <typename T>
+__global__ void dot_kernel(const Run *segs, int n_segs, const T *a, const T *b, double *partial) {
+  double acc = 0.0;
+  SEG_LOOP {
+    const int64_t j = sg.start + i;
+    acc += (double)a[j] * (double)b[j];
+  }
+  block_partial(acc, partial);
+}
+
+// x += alpha p, r -= alpha q; partial <r, r>
+template <typename T>
+__global__ void xr_kernel(const Run *segs, int n_segs, T *x, T *r, const T *p, const T *q, const double *scal,
+                          double *partial) {
+  const T alpha = (T)scal[S_ALPHA];
+  double acc = 0.0;
+  SEG_LOOP {
+    const int64_t j = sg.start + i;
+    x[j] += alpha * p[j];
+    const T rv = r[j] - alpha * q[j];
+    r[j] = rv;
+    acc += (double)rv * (double)rv;
+  }
+  block_partial(acc, partial);
+}
+
+// q = mdiag * x (FP64), the mass part of A x
+__global__ void mass_kernel(const Run *segs, int n_segs, const double *x, const double *mdiag, double *q) {
+  SEG_LOOP {
+    const int64_t j = sg.start + i;
+    q[j] = mdiag[j] * x[j];
+  }
+}
+
+// r = b - q; partial <r, r>
+__global__ void residual_kernel(const Run *segs, int n_segs, const double *b, const double *q, double *r,
+                                double *partial) {
+  double acc = 0.0;
+  SEG_LOOP {
+    const int64_t j = sg.start + i;
+    const double v = b[j] - q[j];
+    r[j] = v;
+    acc += v * v;
+  }
+  block_partial(acc, partial);
+}
+
+// x += (double) e; also zero x (init) when mode == 1
+__global__ void add_kernel(const Run *segs, int n_segs, double *x, const float *e, int zero) {
+  SEG_LOOP {
+    const int64_t j = sg.start + i;
+    x[j] = zero ? 0.0 : x[j] + (double)e[j];
+  }
+}
+
+__global__ void cast_kernel(const Run *segs, int n_segs, const double *a, float *b) {
+  SEG_LOOP {
+    const int64_t j = sg.start + i;
+    b[j] = (float)a[j];
+  }
+}
+
+// mode 0: scal[RR] = s; 1: scal[PQ] = s, scal[ALPHA] = scal[RR] / s;
+// 2: scal[BETA] = s / scal[RR], scal[RR] = s; 3: scal[TMP] = s
+__global__ void reduce_kernel(const double *partial, int n, double *scal, int mode) {
+  __shared__ double red[kBlockThreads];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int i = tid; i < n; i += kBlockThreads) s += partial[i];
+  red[tid] = s;
+  __syncthreads();
+  for (int w = kBlockThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double v = red[0];
+    if (mode == 0) {
+      scal[S_RR] = v;
+    } else if (mode == 1) {
+      scal[S_PQ] = v;
+      scal[S_ALPHA] = scal[S_RR] / v;
+    } else if (mode == 2) {
+      scal[S_BETA] = v / scal[S_RR];
+      scal[S_RR] = v;
+    } else {
+      scal[S_TMP] = v;
+    }
+  }
+}
+
+__global__ void set_gamma_host_kernel(GammaArg g, int k, double *tab64, float *tab32) {
+  const int NN = 2 * k + 1;
+  const double *hscale = tab64 + 2 * k * NN + (k + 1) * (k + 1);
+  for (int idx = threadIdx.x; idx < k * NN; idx += blockDim.x) {
+    const int j = idx / NN;
+    const double v = (g.v[j] * hscale[j]) * tab64[idx];
+    tab64[k * NN + idx] = v;
+    tab32[k * NN + idx] = (float)v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_set_gamma_host(const DevPlan &p, GammaArg g, hipStream_t s) {
+  hipLaunchKernelGGL(set_gamma_host_kernel, dim3(1), dim3(128), 0, s, g, p.k, p.tab64, p.tab32);
+  return hipGetLastError();
+}
+
+struct CgWork {
+  Run *segs = nullptr;
+  int n_segs = 0, n_blocks = 0;
+  double *mdiag = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *scal = nullptr, *partial = nullptr;
+  float *mdiag32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *e32 = nullptr;
+  double *host = nullptr;  // pinned, S_COUNT doubles
+  std::vector<void *> allocs;
+};
+
+void cg_free(CgWork *w) {
+  if (!w) return;
+  for (void *p : w->allocs) (void)hipFree(p);
+  if (w->host) (void)hipHostFree(w->host);
+  delete w;
+}
+
+namespace {
+
+template <typename T>
+hipError_t alloc(CgWork *w, T **p, size_t n) {
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  w->allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return hipSuccess;
+}
+
+hipError_t cg_init(ghost_ctx *ctx, CgWork **out, hipStream_t s) {
+  const Plan &pl = host_plan(ctx);
+  const DevPlan &dp = dev_plan(ctx);
+  CgWork *w = new CgWork;
+  std::vector<Run> segs;
+  for (const Run &r : pl.active_runs)
+    for (int32_t o = 0; o < r.len; o += kSegLen) segs.push_back(Run{r.start + o, std::min(kSegLen, r.len - o), 0});
+  w->n_segs = (int)segs.size();
+  w->n_blocks = std::max(1, (w->n_segs + kSegPerBlock - 1) / kSegPerBlock);
+  const size_t n = (size_t)pl.n_lattice;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = alloc(w, &w->segs, std::max<size_t>(1, segs.size()));
+  if (e == hipSuccess && !segs.empty())
+    e = hipMemcpy(w->segs, segs.data(), segs.size() * sizeof(Run), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = alloc(w, &w->mdiag, n);
+  if (e == hipSuccess) e = alloc(w, &w->r, n);
+  if (e == hipSuccess) e = alloc(w, &w->p, n);
+  if (e == hipSuccess) e = alloc(w, &w->q, n);
+  if (e == hipSuccess) e = alloc(w, &w->scal, S_COUNT);
+  if (e == hipSuccess) e = alloc(w, &w->partial, (size_t)w->n_blocks);
+  if (e == hipSuccess) e = alloc(w, &w->mdiag32, n);
+  if (e == hipSuccess) e = alloc(w, &w->r32, n);
+  if (e == hipSuccess) e = alloc(w, &w->p32, n);
+  if (e == hipSuccess) e = alloc(w, &w->q32, n);
+  if (e == hipSuccess) e = alloc(w, &w->e32, n);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&w->host, S_COUNT * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = launch_mass_diag(dp, w->mdiag, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(cast_kernel, dim3(w->n_blocks), dim3(kBlockThreads), 0, s, w->segs, w->n_segs,
+                       (const double *)w->mdiag, w->mdiag32);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    cg_free(w);
+    return e;
+  }
+  *out = w;
+  return hipSuccess;
+}
+
+struct Runner {
+  const DevPlan &dp;
+  CgWork *w;
+  hipStream_t s;
+  hipError_t err = hipSuccess;
+  dim3 grid, block{kBlockThreads};
+  Runner(const DevPlan &d, CgWork *w_, hipStream_t s_) : dp(d), w(w_), s(s_), grid(w_->n_blocks) {}
+  void reduce(int mode) {
+    if (err != hipSuccess) return;
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlockThreads), 0, s, w->partial, w->n_blocks, w->scal, mode);
+    err = hipGetLastError();
+  }
+  void check() {
+    if (err == hipSuccess) err = hipGetLastError();
+  }
+  double read(int idx) {
+    if (err != hipSuccess) return NAN;
+    err = hipMemcpyAsync(w->host, w->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    return err == hipSuccess ? w->host[idx] : NAN;
+  }
+  // r = b - A x (FP64), rr -> scal[mode target]; returns |r|^2
+  double true_residual(const double *b, const double *x, double *r) {
+    hipLaunchKernelGGL(mass_kernel, grid, block, 0, s, w->segs, w->n_segs, x, (const double *)w->mdiag, w->q);
+    check();
+    if (err == hipSuccess) err = launch_apply_f64(dp, x, w->q, true, s);
+    hipLaunchKernelGGL(residual_kernel, grid, block, 0, s, w->segs, w->n_segs, b, (const double *)w->q, r,
+                       w->partial);
+    check();
+    reduce(0);
+    return read(S_RR);
+  }
+};
+
+}  // namespace
+
+int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &opts, ghost_cg_result &res,
+             hipStream_t s) {
+  res = ghost_cg_result{0, 0, 0, NAN};
+  CgWork *&slot = cg_slot(ctx);
+  if (!slot) {
+    hipError_t e = cg_init(ctx, &slot, s);
+    if (e != hipSuccess) {
+      slot = nullptr;
+      return set_error(e == hipErrorOutOfMemory ? GHOST_ENOMEM : GHOST_EHIP, hipGetErrorString(e));
+    }
+  }
+  CgWork *w = slot;
+  const DevPlan &dp = dev_plan(ctx);
+  Runner R(dp, w, s);
+  const dim3 grid(w->n_blocks), block(kBlockThreads);
+
+  // |b|
+  hipLaunchKernelGGL(dot_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, b, b, w->partial);
+  R.check();
+  R.reduce(3);
+  const double bnorm = std::sqrt(R.read(S_TMP));
+  if (R.err != hipSuccess) return set_error(GHOST_EHIP, hipGetErrorString(R.err));
+  const double target = opts.tol * bnorm;
+  int it = 0;
+
+  if (opts.mode == GHOST_CG_FP64) {
+    hipLaunchKernelGGL(start_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, b, x, w->r, w->p, w->partial);
+    R.check();
+    R.reduce(0);
+    double rr = R.read(S_RR);
+    const int every = opts.check_every > 0 ? opts.check_every : 50;
+    bool update_p = false;
+    while (R.err == hipSuccess && std::sqrt(rr) > target && it < opts.max_iter) {
+      hipLaunchKernelGGL(pq_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, w->p, (const double *)w->r,
+                         w->q, (const double *)w->mdiag, (const double *)w->scal, (int)update_p);
+      R.check();
+      if (R.err == hipSuccess) R.err = launch_apply_f64(dp, w->p, w->q, true, s);
+      hipLaunchKernelGGL(dot_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, (const double *)w->p,
+                         (const double *)w->q, w->partial);
+      R.check();
+      R.reduce(1);
+      hipLaunchKernelGGL(xr_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, x, w->r, (const double *)w->p,
+                         (const double *)w->q, (const double *)w->scal, w->partial);
+      R.check();
+      R.reduce(2);
+      update_p = true;
+      ++it;
+      rr = R.read(S_RR);
+      if (std::sqrt(rr) <= target || it % every == 0) {
+        // replace the recursive residual by the true one (the search direction is kept)
+        rr = R.true_residual(b, x, w->r);
+      }
+    }
+    res.outer = 1;
+  } else {
+    hipLaunchKernelGGL(add_kernel, grid, block, 0, s, w->segs, w->n_segs, x, (const float *)nullptr, 1);
+    R.check();
+    while (R.err == hipSuccess) {
+      const double rr_true = R.true_residual(b, x, w->r);
+      if (!(std::sqrt(rr_true) > target) || it >= opts.max_iter) break;
+      // inner FP32 CG on A e = r
+      hipLaunchKernelGGL(start_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, (const double *)w->r, w->e32,
+                         w->r32, w->p32, w->partial);
+      R.check();
+      R.reduce(0);
+      double rr = R.read(S_RR);
+      const double inner_target = opts.inner_tol * std::sqrt(rr);
+      bool update_p = false;
+      while (R.err == hipSuccess && std::sqrt(rr) > inner_target && it < opts.max_iter) {
+        hipLaunchKernelGGL(pq_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, w->p32, (const float *)w->r32,
+                           w->q32, (const float *)w->mdiag32, (const double *)w->scal, (int)update_p);
+        R.check();
+        if (R.err == hipSuccess) R.err = launch_apply_f32(dp, w->p32, w->q32, true, s);
+        hipLaunchKernelGGL(dot_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, (const float *)w->p32,
+                           (const float *)w->q32, w->partial);
+        R.check();
+        R.reduce(1);
+        hipLaunchKernelGGL(xr_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, w->e32, w->r32,
+                           (const float *)w->p32, (const float *)w->q32, (const double *)w->scal, w->partial);
+        R.check();
+        R.reduce(2);
+        update_p = true;
+        ++it;
+        rr = R.read(S_RR);
+        if (!std::isfinite(rr)) break;
+      }
+      hipLaunchKernelGGL(add_kernel, grid, block, 0, s, w->segs, w->n_segs, x, (const float *)w->e32, 0);
+      R.check();
+      ++res.outer;
+    }
+  }
+  if (R.err != hipSuccess) return set_error(GHOST_EHIP, hipGetErrorString(R.err));
+  const double rr_final = R.true_residual(b, x, w->r);
+  if (R.err != hipSuccess) return set_error(GHOST_EHIP, hipGetErrorString(R.err));
+  res.iterations = it;
+  res.rel_residual = bnorm > 0 ? std::sqrt(rr_final) / bnorm : 0.0;
+  res.converged = res.rel_residual <= opts.tol;
+  return GHOST_OK;
+}
+
+}  // namespace ghost

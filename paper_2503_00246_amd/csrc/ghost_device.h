@@ -1,0 +1,56 @@
+// Device-side view of a plan and the kernel launchers (implemented in ghost_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "ghost_plan.h"
+
+namespace ghost {
+
+// Layout of the per-context table buffers (offsets in elements of the precision):
+//   [0, k*NN)            g   : reference jump vectors, row j-1 = order j
+//   [k*NN, 2*k*NN)       gs  : gamma_j h^{d-1-2j} g_j, the expansion coefficients of one face
+//   [2*k*NN, +K*K)       M   : reference mass matrix
+//   FP64 buffer only: [.., +k) hscale_j = h^{d-1-2j}, then [.., +K) GLL weights on [0, 1]
+inline int tab_gs(int k) { return k * (2 * k + 1); }
+inline int tab_M(int k) { return 2 * k * (2 * k + 1); }
+inline int tab_hscale(int k) { return 2 * k * (2 * k + 1) + (k + 1) * (k + 1); }
+inline int tab_gllw(int k) { return tab_hscale(k) + k; }
+inline int tab_size64(int k) { return tab_gllw(k) + k + 1; }
+inline int tab_size32(int k) { return tab_hscale(k); }
+
+struct DevPlan {
+  int dim = 0, k = 0;
+  int32_t stride[3] = {1, 1, 1};
+  int n[3] = {1, 1, 1};
+  int64_t L[3] = {1, 1, 1};
+  double h = 0;
+
+  const int64_t *face_base = nullptr;
+  const Batch *batches = nullptr;
+  int n_batches = 0;
+  bool coloured = false;
+  int n_colours = 0;
+  const int *colour_begin = nullptr;  // host array, n_colours + 1
+
+  const Run *support_runs = nullptr;
+  int n_support_runs = 0;
+  const Run *active_runs = nullptr;
+  int n_active_runs = 0;
+  const int8_t *cls = nullptr;        // device cell classes
+
+  double *tab64 = nullptr;
+  float *tab32 = nullptr;
+  double *vjp_partial = nullptr;      // n_batches * k doubles
+};
+
+hipError_t launch_apply_f64(const DevPlan &p, const double *u, double *y, bool accumulate, hipStream_t s);
+hipError_t launch_apply_f32(const DevPlan &p, const float *u, float *y, bool accumulate, hipStream_t s);
+hipError_t launch_vjp(const DevPlan &p, const double *u, const double *w, double *du, double *dgamma,
+                      bool accumulate, hipStream_t s);
+hipError_t launch_set_gamma(const DevPlan &p, const double *gamma_dev, hipStream_t s);
+hipError_t launch_mass_diag(const DevPlan &p, double *diag, hipStream_t s);
+
+}  // namespace ghost

@@ -1,0 +1,191 @@
+"""Python face of libghost: GhostOperator and cg_solve.
+
+PyTorch supplies device memory and the current HIP stream; every operation is
+a call into the HIP library (include/ghost.h).
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class GhostOperator:
+    """Matrix-free ghost penalty y = G(gamma) u on a Cartesian mesh cut by a level set.
+
+    d, n, lo, h: mesh (cells per axis, lower corner, cell side); k: degree;
+    gamma: k coefficients; either (centre, radius) of a ball, or cell_class
+    (x-fastest array of 0 outside / 1 inside / 2 cut).  device=-1 builds a
+    host-only plan (inspection without a GPU).
+    """
+
+    def __init__(self, d, n, lo, h, k, gamma, centre=None, radius=None, cell_class=None,
+                 coloured=False, device=0):
+        lib = L.load()
+        mesh = L.GhostMesh()
+        mesh.dim = d
+        for a in range(3):
+            mesh.n[a] = int(n[a]) if a < d else 1
+            mesh.lo[a] = float(lo[a]) if a < d else 0.0
+        mesh.h = float(h)
+        ls = L.GhostLevelset()
+        self._cls_keep = None
+        if cell_class is not None:
+            ls.kind = L.GHOST_LS_CELLS
+            arr = np.ascontiguousarray(np.asarray(cell_class, dtype=np.int8).ravel())
+            self._cls_keep = arr
+            ls.cell_class = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_byte))
+        else:
+            ls.kind = L.GHOST_LS_BALL
+            for a in range(3):
+                ls.centre[a] = float(centre[a]) if a < d else 0.0
+            ls.radius = float(radius)
+        g = (ctypes.c_double * k)(*[float(x) for x in gamma])
+        flags = L.GHOST_FP64 | L.GHOST_FP32 | (L.GHOST_COLOURED if coloured else 0)
+        handle = ctypes.c_void_p()
+        L.check(lib.ghost_setup(ctypes.byref(mesh), ctypes.byref(ls), int(k), g, flags, int(device),
+                                ctypes.byref(handle)))
+        self._h = handle
+        self._lib = lib
+        self.d, self.k, self.device = d, k, device
+        self.gamma = [float(x) for x in gamma]
+        st = L.GhostStats()
+        L.check(lib.ghost_info(self._h, ctypes.byref(st)))
+        self.stats = st.as_dict()
+        self.n_lattice = self.stats["n_lattice"]
+
+    @classmethod
+    def from_workload(cls, w, coloured=False, device=0, gamma=None):
+        return cls(w.d, w.n, w.lo, w.h, w.k, w.gamma() if gamma is None else gamma,
+                   centre=w.centre, radius=w.radius, coloured=coloured, device=device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ghost_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ checks
+    def _vec(self, t, dtype, name):
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if t.device.type != "cuda" or t.device.index != self.device:
+            raise ValueError(f"{name} must live on cuda:{self.device}")
+        if not t.is_contiguous() or t.numel() != self.n_lattice:
+            raise ValueError(f"{name} must be contiguous with {self.n_lattice} entries")
+        return t
+
+    def _dev(self):
+        import torch
+        return torch.device("cuda", self.device)
+
+    # ------------------------------------------------------------------ operations
+    def apply(self, u, y=None, accumulate=False):
+        """y (+)= G u in FP64.  Without y a zeroed output is allocated."""
+        import torch
+        self._vec(u, torch.float64, "u")
+        if y is None:
+            y = torch.zeros_like(u)
+        self._vec(y, torch.float64, "y")
+        L.check(self._lib.ghost_apply(self._h, _ptr(u), _ptr(y), int(accumulate), _stream(self._dev())))
+        return y
+
+    def apply_f32(self, u, y=None, accumulate=False):
+        import torch
+        self._vec(u, torch.float32, "u")
+        if y is None:
+            y = torch.zeros_like(u)
+        self._vec(y, torch.float32, "y")
+        L.check(self._lib.ghost_apply_f32(self._h, _ptr(u), _ptr(y), int(accumulate), _stream(self._dev())))
+        return y
+
+    def vjp(self, u, w, du=None, accumulate=False):
+        """(G w, [w^T G_j u]_j) for the pull-back of w through y = G(gamma) u."""
+        import torch
+        self._vec(u, torch.float64, "u")
+        self._vec(w, torch.float64, "w")
+        if du is None:
+            du = torch.zeros_like(u)
+        self._vec(du, torch.float64, "du")
+        dg = torch.empty(self.k, dtype=torch.float64, device=self._dev())
+        L.check(self._lib.ghost_vjp(self._h, _ptr(u), _ptr(w), _ptr(du), _ptr(dg), int(accumulate),
+                                    _stream(self._dev())))
+        return du, dg
+
+    def set_gamma(self, gamma):
+        """Replace gamma: a host sequence (validated) or a float64 CUDA tensor of k values (stream-ordered)."""
+        import torch
+        if isinstance(gamma, torch.Tensor) and gamma.device.type == "cuda":
+            if gamma.dtype != torch.float64 or gamma.numel() != self.k or not gamma.is_contiguous():
+                raise ValueError("device gamma must be a contiguous float64 tensor of k values")
+            L.check(self._lib.ghost_set_gamma(self._h, _ptr(gamma), 1, _stream(self._dev())))
+            return
+        vals = [float(x) for x in (gamma.tolist() if hasattr(gamma, "tolist") else gamma)]
+        if len(vals) != self.k:
+            raise ValueError("need k coefficients")
+        arr = (ctypes.c_double * self.k)(*vals)
+        L.check(self._lib.ghost_set_gamma(self._h, ctypes.cast(arr, ctypes.c_void_p), 0, _stream(self._dev())))
+        self.gamma = vals
+
+    def mass_diag(self):
+        import torch
+        out = torch.empty(self.n_lattice, dtype=torch.float64, device=self._dev())
+        L.check(self._lib.ghost_mass_diag(self._h, _ptr(out), _stream(self._dev())))
+        return out
+
+    def cg(self, b, x=None, mode="fp64", tol=1e-10, max_iter=20000, inner_tol=1e-4, check_every=50):
+        """Solve (M + G) x = b on the active nodes; returns (x, result dict).  Synchronous."""
+        import torch
+        self._vec(b, torch.float64, "b")
+        if x is None:
+            x = torch.zeros_like(b)
+        self._vec(x, torch.float64, "x")
+        opts = L.GhostCgOpts()
+        opts.mode = {"fp64": L.GHOST_CG_FP64, "mixed": L.GHOST_CG_MIXED}[mode]
+        opts.tol, opts.max_iter, opts.inner_tol, opts.check_every = tol, max_iter, inner_tol, check_every
+        res = L.GhostCgResult()
+        L.check(self._lib.ghost_cg(self._h, _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(res),
+                                   _stream(self._dev())))
+        return x, {"iterations": res.iterations, "outer": res.outer, "converged": bool(res.converged),
+                   "rel_residual": res.rel_residual}
+
+    # ------------------------------------------------------------------ inspection (host)
+    def faces(self, axis):
+        """(nf, 4) int32: lower-cell multi-index c0, c1, c2 and colour (-1 if not coloured)."""
+        nf = self.stats["n_faces"][axis]
+        out = np.zeros((max(nf, 1), 4), dtype=np.int32)
+        L.check(self._lib.ghost_faces(self._h, axis, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nf))
+        return out[:nf]
+
+    def tables(self):
+        k = self.k
+        jumps = np.zeros((k, 2 * k + 1))
+        mass = np.zeros((k + 1, k + 1))
+        nodes = np.zeros(k + 1)
+        weights = np.zeros(k + 1)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.check(self._lib.ghost_tables(self._h, jumps.ctypes.data_as(dp), mass.ctypes.data_as(dp),
+                                       nodes.ctypes.data_as(dp), weights.ctypes.data_as(dp)))
+        return {"jumps": jumps, "mass": mass, "nodes": nodes, "weights": weights}
+
+
+def cg_solve(op, b, mode="fp64", **kw):
+    return op.cg(b, mode=mode, **kw)

@@ -1,0 +1,125 @@
+"""GPU tests of ghost_vjp, the autograd wrapper, the lumped mass and ghost_cg (through the C ABI)."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle.operator import GhostOracle, cg_reference
+from paper_2503_00246_amd.workloads import (WORKLOADS, SEED_B, SEED_FD, SEED_T, SEED_U, Workload, submesh_q4_16,
+                                            uniform_vector)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def gpu_op(w, **kw):
+    from paper_2503_00246_amd.operator import GhostOperator
+    return GhostOperator.from_workload(w, **kw)
+
+
+def oracle(w, per_face=False):
+    return GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), centre=w.centre, radius=w.radius, per_face=per_face)
+
+
+def test_vjp_matches_oracle_gradient_on_submesh():
+    """16^3 block of the 96^3 Q4 mesh: the oracle's exact sparse gradients of L = 0.5|G u - t|^2."""
+    w = submesh_q4_16()
+    o = oracle(w)
+    assert o.n_faces() > 50
+    u = uniform_vector(w.n_lattice, SEED_U)
+    t = uniform_vector(w.n_lattice, SEED_T)
+    _, du_ref, dg_ref = o.gradients(u, t)
+    op = gpu_op(w)
+    ut, tt = torch.from_numpy(u).cuda(), torch.from_numpy(t).cuda()
+    r = op.apply(ut) - tt
+    du, dg = op.vjp(ut, r)
+    du, dg = du.cpu().numpy(), dg.cpu().numpy()
+    assert np.max(np.abs(du - du_ref)) <= 1e-12 * np.max(np.abs(du_ref))
+    np.testing.assert_allclose(dg, dg_ref, rtol=1e-12, atol=0)
+
+
+def test_vjp_finite_differences_full_mesh():
+    """ball3d_q4_96: central differences of L in u (3 seeded directions, step 1e-6) and in each gamma_j
+    (relative step 1e-6), formed as sum (y+ - y-)(y+ + y- - 2t)/2 to avoid cancellation."""
+    w = WORKLOADS["ball3d_q4_96"]
+    op = gpu_op(w)
+    u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda()
+    t = torch.from_numpy(uniform_vector(w.n_lattice, SEED_T)).cuda()
+    y = op.apply(u)
+    du, dg = op.vjp(u, y - t)
+
+    def dL(yp, ym, step):
+        return float(((yp - ym) * (yp + ym - 2 * t)).sum()) / 2 / (2 * step)
+
+    rng = np.random.default_rng(SEED_FD)
+    for _ in range(3):
+        v = torch.from_numpy(rng.uniform(-1, 1, w.n_lattice)).cuda()
+        eps = 1e-6
+        fd = dL(op.apply(u + eps * v), op.apply(u - eps * v), eps)
+        an = float(du @ v)
+        assert abs(fd - an) <= 1e-6 * abs(an)
+    g0 = list(w.gamma())
+    for j in range(w.k):
+        step = 1e-6 * g0[j]
+        gp, gm = list(g0), list(g0)
+        gp[j] += step
+        gm[j] -= step
+        op.set_gamma(gp)
+        yp = op.apply(u)
+        op.set_gamma(gm)
+        ym = op.apply(u)
+        fd = dL(yp, ym, step)
+        assert abs(fd - float(dg[j])) <= 1e-6 * abs(float(dg[j])), j
+    op.set_gamma(g0)
+    # adjoint identity on the full mesh
+    wv = torch.from_numpy(uniform_vector(w.n_lattice, 21)).cuda()
+    a_, b_ = float(wv @ op.apply(u)), float(op.apply(wv) @ u)
+    assert abs(a_ - b_) <= 1e-12 * abs(a_)
+
+
+def test_autograd_function():
+    from paper_2503_00246_amd.autograd import ghost_apply
+    w = Workload("small_q3_12", 3, 3, (12,) * 3, (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)
+    op = gpu_op(w)
+    u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda().requires_grad_(True)
+    t = torch.from_numpy(uniform_vector(w.n_lattice, SEED_T)).cuda()
+    gamma = torch.tensor(w.gamma(), dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = 0.5 * ((ghost_apply(u, gamma, op) - t) ** 2).sum()
+    loss.backward()
+    o = oracle(w)
+    _, du_ref, dg_ref = o.gradients(u.detach().cpu().numpy(), t.cpu().numpy())
+    assert float((u.grad.cpu() - torch.from_numpy(du_ref)).abs().max()) <= 1e-12 * np.abs(du_ref).max()
+    np.testing.assert_allclose(gamma.grad.cpu().numpy(), dg_ref, rtol=1e-12)
+    # device gamma drives the forward: doubling gamma doubles y
+    y1 = ghost_apply(u.detach(), gamma.detach(), op)
+    y2 = ghost_apply(u.detach(), 2 * gamma.detach(), op)
+    assert float((y2 - 2 * y1).abs().max()) <= 1e-13 * float(y1.abs().max())
+
+
+@pytest.mark.parametrize("w", [WORKLOADS["disk2d_q2_32"],
+                               Workload("small_q3_12", 3, 3, (12,) * 3, (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)],
+                         ids=lambda w: w.name)
+def test_mass_diag(w):
+    o = oracle(w)
+    m = gpu_op(w).mass_diag().cpu().numpy()
+    ref = o.lumped_mass()
+    assert np.max(np.abs(m - ref)) <= 1e-15 * np.max(ref)
+    assert np.all((m > 0) == (ref > 0))
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_cg_small(mode):
+    w = Workload("small_q3_12", 3, 3, (12,) * 3, (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)
+    o = oracle(w)
+    A, active = o.system()
+    b = np.zeros(w.n_lattice)
+    b[active] = uniform_vector(w.n_lattice, SEED_B)[active]
+    op = gpu_op(w)
+    x, res = op.cg(torch.from_numpy(b).cuda(), mode=mode, tol=1e-10, max_iter=20000)
+    x = x.cpu().numpy()
+    rel = np.linalg.norm(b[active] - A @ x[active]) / np.linalg.norm(b[active])
+    assert res["converged"] and rel <= 1.5e-10 and abs(rel - res["rel_residual"]) <= 1e-3 * rel + 1e-11
+    xr, it, rr = cg_reference(A, b[active], tol=1e-10)
+    # parity of x beyond the residual is bounded by the conditioning; compare loosely
+    assert np.linalg.norm(x[active] - xr) <= 1e-4 * np.linalg.norm(xr)

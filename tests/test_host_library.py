@@ -1,0 +1,184 @@
+"""CPU tests of libghost's host side: exports, plan vs the oracle, colouring, error paths.
+
+No GPU is touched: contexts are built with device = -1 (host-only plans).
+"""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import mesh as omesh, patch as opatch
+from oracle.basis import gll_nodes, gll_weights
+from oracle.operator import GhostOracle
+from paper_2503_00246_amd import _lib as L
+from paper_2503_00246_amd.operator import GhostOperator
+from paper_2503_00246_amd.workloads import WORKLOADS, gamma_paper
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    with open(os.path.join(ROOT, "include", "ghost.h")) as f:
+        text = f.read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(ghost_\w+)\s*\(", text, re.M))
+    assert declared == set(L.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+def _host(w, coloured=False, **kw):
+    return GhostOperator.from_workload(w, coloured=coloured, device=-1, **kw)
+
+
+@pytest.mark.parametrize("k", range(1, 8))
+def test_tables_match_oracle(k):
+    w = WORKLOADS["disk2d_q2_32"]
+    op = GhostOperator(2, w.n, w.lo, w.h, k, gamma_paper(k, w.h), centre=w.centre, radius=w.radius, device=-1)
+    t = op.tables()
+    J = opatch.jump_vectors_reference(k)
+    jumps = np.array([[float(v) for v in J[j]] for j in range(1, k + 1)])
+    mass = np.array([[float(v) for v in r] for r in opatch.mass_reference(k)])
+    np.testing.assert_allclose(t["jumps"], jumps, rtol=0, atol=2e-16 * np.abs(jumps).max())
+    np.testing.assert_allclose(t["mass"], mass, rtol=0, atol=2e-16)
+    np.testing.assert_allclose(t["nodes"], [float(x) for x in gll_nodes(k)], rtol=0, atol=2e-16)
+    np.testing.assert_allclose(t["weights"], [float(x) for x in gll_weights(k)], rtol=0, atol=2e-16)
+
+
+@pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64"])
+def test_plan_matches_oracle(name):
+    w = WORKLOADS[name]
+    op = _host(w)
+    cls = omesh.classify_ball(w.n, w.lo, w.h, w.centre, w.radius)
+    faces = omesh.ghost_faces(cls)
+    st = op.stats
+    assert st["n_active_cells"] == int(np.sum(cls != 0))
+    assert st["n_cut_cells"] == int(np.sum(cls == 2))
+    for a in range(w.d):
+        got = op.faces(a)[:, :w.d]
+        np.testing.assert_array_equal(got, faces[a])
+        assert st["n_faces"][a] == len(faces[a])
+    assert st["n_patch_dofs"] == w.n_p
+    assert st["n_lattice"] == w.n_lattice
+    # support = union of the patches, active = nodes of active cells
+    L_ = w.lattice
+    sup = np.unique(np.concatenate([omesh.patch_dofs(faces[a], w.k, a, L_).ravel() for a in range(w.d)]))
+    assert st["n_support_dofs"] == len(sup)
+    assert st["bytes_fp64"] == 24 * len(sup)
+    if w.d == 2:
+        o = GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), centre=w.centre, radius=w.radius)
+        assert st["n_active_dofs"] == int(np.sum(o.lumped_mass() > 0))
+
+
+def test_flop_count_formula():
+    """Rank-k cost per face: 2k(2k+1)(k+1)^{d-1} + (d-1)k(k+1)^d FMAs (2 flops each)."""
+    for name in ["disk2d_q2_32", "ball3d_q3_64"]:
+        w = WORKLOADS[name]
+        k, d = w.k, w.d
+        fma = 2 * k * (2 * k + 1) * (k + 1) ** (d - 1) + (d - 1) * k * (k + 1) ** d
+        assert _host(w).stats["flops_per_face"] == 2 * fma
+
+
+@pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64"])
+def test_colouring_is_race_free(name):
+    """No two faces of one colour share a lattice node (exact check with the oracle's patch numbering)."""
+    w = WORKLOADS[name]
+    op = _host(w, coloured=True)
+    per_axis = 3 * 2 ** (w.d - 1)
+    assert op.stats["n_colours"] == w.d * per_axis
+    owner = {}
+    for a in range(w.d):
+        f = op.faces(a)
+        dofs = omesh.patch_dofs(f[:, :w.d].astype(np.int64), w.k, a, w.lattice)
+        for col in np.unique(f[:, 3]):
+            sel = f[:, 3] == col
+            flat = dofs[sel].ravel()
+            assert len(np.unique(flat)) == len(flat), f"colour {col} has a shared node"
+            owner[col] = owner.get(col, 0) + sel.sum()
+    assert sum(owner.values()) == op.stats["n_faces_total"]
+
+
+def test_cell_class_level_set_matches_ball():
+    w = WORKLOADS["disk2d_q2_32"]
+    cls = omesh.classify_ball(w.n, w.lo, w.h, w.centre, w.radius)
+    flat = cls.ravel(order="F")  # x fastest
+    a = _host(w)
+    b = GhostOperator(2, w.n, w.lo, w.h, w.k, w.gamma(), cell_class=flat, device=-1)
+    for ax in range(2):
+        np.testing.assert_array_equal(a.faces(ax), b.faces(ax))
+    assert a.stats["n_support_dofs"] == b.stats["n_support_dofs"]
+
+
+def test_empty_face_set_is_valid():
+    """A ball strictly inside one cell's neighbourhood without ghost faces: zero faces, valid plan."""
+    op = GhostOperator(2, (8, 8), (-1, -1), 0.25, 2, [1.0, 1.0], centre=(5.0, 5.0), radius=0.1, device=-1)
+    assert op.stats["n_faces_total"] == 0 and op.stats["n_support_dofs"] == 0
+
+
+def _raw_setup(lib, dim=2, n=(8, 8, 8), h=0.25, k=2, gamma=(1.0, 1.0), kind=0, radius=0.5, flags=0, device=-1,
+               cls=None, null=None):
+    m = L.GhostMesh()
+    m.dim = dim
+    for a in range(3):
+        m.n[a] = n[a]
+        m.lo[a] = -1.0
+    m.h = h
+    ls = L.GhostLevelset()
+    ls.kind = kind
+    ls.radius = radius
+    if cls is not None:
+        ls.cell_class = cls
+    g = (ctypes.c_double * max(1, len(gamma)))(*gamma)
+    out = ctypes.c_void_p()
+    args = [ctypes.byref(m), ctypes.byref(ls), k, g, flags, device, ctypes.byref(out)]
+    if null is not None:
+        args[null] = None
+    rc = lib.ghost_setup(*args)
+    if rc == 0:
+        lib.ghost_destroy(out)
+    return rc, lib.ghost_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(dim=4), "dim"), (dict(k=0), "k must"), (dict(k=8, gamma=(1.0,) * 8), "k must"),
+    (dict(n=(1, 8, 8)), "n[0]"), (dict(h=0.0), "h must"), (dict(h=float("nan")), "h must"),
+    (dict(gamma=(1.0, -1.0)), "gamma"), (dict(gamma=(1.0, float("inf"))), "gamma"),
+    (dict(radius=-1.0), "radius"), (dict(kind=7), "kind"), (dict(kind=1), "cell_class"),
+    (dict(flags=64), "flags"), (dict(device=-2), "device"), (dict(null=0), "null"), (dict(null=3), "null"),
+    (dict(null=6), "out"),
+])
+def test_setup_rejects_bad_arguments(lib, kw, needle):
+    rc, msg = _raw_setup(lib, **kw)
+    assert rc == L.GHOST_EINVAL and needle in msg, msg
+
+
+def test_bad_cell_class_value(lib):
+    cls = (ctypes.c_byte * 64)(*([0] * 63 + [5]))
+    rc, msg = _raw_setup(lib, kind=1, cls=ctypes.cast(cls, ctypes.POINTER(ctypes.c_byte)))
+    assert rc == L.GHOST_EINVAL and "cell_class" in msg
+
+
+def test_host_only_context_refuses_device_work(lib):
+    w = WORKLOADS["disk2d_q2_32"]
+    op = _host(w)
+    p = ctypes.c_void_p(16)
+    q = ctypes.c_void_p(1 << 40)
+    assert lib.ghost_apply(op._h, p, q, 0, None) == L.GHOST_ESTATE
+    assert lib.ghost_apply_f32(op._h, p, q, 0, None) == L.GHOST_ESTATE
+    assert lib.ghost_vjp(op._h, p, p, q, q, 0, None) == L.GHOST_ESTATE
+    assert lib.ghost_mass_diag(op._h, p, None) == L.GHOST_ESTATE
+    assert lib.ghost_set_gamma(op._h, p, 0, None) == L.GHOST_ESTATE
+    assert lib.ghost_apply(None, p, q, 0, None) == L.GHOST_EINVAL
+    assert lib.ghost_info(None, None) == L.GHOST_EINVAL
+    small = np.zeros((1, 4), dtype=np.int32)
+    assert lib.ghost_faces(op._h, 0, small.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 1) == L.GHOST_EINVAL
+    assert lib.ghost_faces(op._h, 5, small.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 1) == L.GHOST_EINVAL
+    lib.ghost_destroy(None)  # no-op
