@@ -16,6 +16,7 @@ the stream the kernel runs on.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -23,6 +24,14 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(ROOT, "paper_2503_00246_amd", "csrc", "ghost_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def parse():
@@ -31,11 +40,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="ball3d_q5_128")
-    ap.add_argument("--coloured", action="store_true", help="race-free colour scatter instead of atomics")
+    ap.add_argument("--scatter", default="owner", choices=["owner", "atomic", "coloured"])
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run one plain device copy of u (known bytes) to scale PMC byte counters")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="one JSON line per degree/mesh of the roofline sweep")
-    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
+    ap.add_argument("--traffic", default=TRAFFIC_FILE, help="JSON file with measured HBM bytes per launch")
     return ap.parse_args()
 
 
@@ -55,21 +66,28 @@ def timed_applies(fn, steps, warmup):
     return start.elapsed_time(end) / 1e3 / steps  # seconds per step
 
 
-def cpu_baseline(w, u_np):
-    """The oracle's apply on the same workload, timed on the host cores (assembly excluded)."""
-    import numpy as np
+def cpu_baseline(w, u_np, budget_s=10.0):
+    """The oracle's apply on the same workload, repeated for about budget_s on the host cores.
+
+    The oracle's own set-up (classification, face set, quadrature assembly of the patch matrices)
+    is excluded; each repetition is one full apply (gather, dense patch matvec by BLAS, scatter-add).
+    """
     from threadpoolctl import threadpool_info
     from oracle.operator import GhostOracle
     o = GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), centre=w.centre, radius=w.radius)
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    t0 = time.perf_counter()
-    o.apply(u_np)
-    dt = time.perf_counter() - t0
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        o.apply(u_np)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            break
     faces = o.n_faces()
-    return {"value": round(faces * w.n_p / dt / 1e9, 6), "unit": "GDoF/s", "cores": threads, "kind": "oracle",
-            "sample": f"one full oracle apply of {w.name} ({faces} faces, dense per-face patch matvec "
-                      f"by BLAS + scatter-add), {dt:.1f} s, host {platform.processor() or platform.machine()}, "
-                      f"{os.cpu_count()} logical CPUs"}
+    return {"value": round(reps * faces * w.n_p / dt / 1e9, 6), "unit": "GDoF/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} full oracle applies of {w.name} ({faces} faces each: dense per-face patch matvec "
+                      f"by BLAS + scatter-add) in {dt:.1f} s; host {platform.processor() or platform.machine()}, "
+                      f"{os.cpu_count()} logical CPUs, BLAS threads {threads}"}
 
 
 def run_workload(w, args, with_cpu):
@@ -78,7 +96,7 @@ def run_workload(w, args, with_cpu):
     from paper_2503_00246_amd.operator import GhostOperator
     from paper_2503_00246_amd.workloads import SEED_U, uniform_vector
 
-    op = GhostOperator.from_workload(w, coloured=args.coloured)
+    op = GhostOperator.from_workload(w, scatter=args.scatter)
     st = op.stats
     u_np = uniform_vector(w.n_lattice, SEED_U)
     u = torch.from_numpy(u_np).cuda()
@@ -94,6 +112,11 @@ def run_workload(w, args, with_cpu):
         got = op.apply_f32(u32).double()
         err = float((got - ref).abs().max() / ref.abs().max())
         out.update(t32=t32, gdofs32=patch_dofs / t32 / 1e9, err32=err)
+    if args.calibrate:
+        c = torch.empty_like(u)
+        c.copy_(u)  # one plain copy: n_lattice * 8 bytes read and written
+        torch.cuda.synchronize()
+        out["copy_bytes"] = 8 * w.n_lattice
     if with_cpu:
         out["cpu"] = cpu_baseline(w, u_np)
     del u, y
@@ -130,7 +153,10 @@ def main():
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
         with open(args.traffic) as f:
-            traffic = json.load(f).get(w.name)
+            rec = json.load(f).get(f"{w.name}/{args.scatter}/f64")
+        # measured bytes are only valid for the kernel source they were taken with
+        if rec and rec.get("kernel_sha") == kernel_hash():
+            traffic = rec["bytes_per_launch"]
     line = {
         "metric": "ghost-face patch DoFs/s for G.u (GDoF/s), FP64 vs FP32 at stated error, d=3",
         "value": round(r["gdofs64"], 4),
@@ -147,7 +173,7 @@ def main():
         "config": {"workload": w.name, "d": w.d, "k": w.k, "cells_per_axis": w.n[0],
                    "faces": st["n_faces_total"], "patch_dofs_per_face": st["n_patch_dofs"],
                    "support_dofs": st["n_support_dofs"], "lattice_dofs": st["n_lattice"],
-                   "scatter": "colour" if args.coloured else "atomic", "mode": "accumulate"},
+                   "scatter": args.scatter, "mode": "accumulate"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "fp32": None if "t32" not in r else {

@@ -62,7 +62,11 @@ extern "C" {
 /* ghost_setup flags */
 #define GHOST_FP64 1u     /* accepted for clarity; both precisions are always built */
 #define GHOST_FP32 2u
-#define GHOST_COLOURED 4u /* scatter by race-free face colouring instead of FP64/FP32 atomics */
+#define GHOST_COLOURED 4u /* scatter strategy: face-parallel, plain read-modify-write per race-free colour */
+#define GHOST_ATOMIC 8u   /* scatter strategy: face-parallel, hardware FP64/FP32 atomics */
+/* With neither flag the default owner-computes scatter is used: each workgroup owns a box of
+ * lattice nodes, applies every face whose patch meets the box, accumulates in LDS and writes each
+ * owned node once (no atomics, deterministic). */
 
 typedef struct ghost_ctx ghost_ctx;
 
@@ -92,7 +96,11 @@ typedef struct {
   int64_t n_faces[3];         /* ghost faces per normal axis */
   int64_t n_faces_total;
   int64_t n_patch_dofs;       /* (2k+1)(k+1)^(d-1) nodes per face patch */
-  int64_t n_batches;          /* workgroups of one apply launch */
+  int64_t n_batches;          /* workgroups of one face-parallel launch */
+  int64_t n_boxes;            /* owner-computes: node boxes (workgroups of one launch) */
+  int64_t n_visits;           /* owner-computes: face visits (>= n_faces_total; faces crossing boxes repeat) */
+  int brick;                  /* owner-computes: box edge in cells before splitting */
+  int max_acc;                /* owner-computes: largest LDS accumulator (entries) */
   double flops_per_face;      /* arithmetic of one face in the kernel, 2 per FMA */
   double bytes_fp64;          /* compulsory bytes of an accumulating FP64 apply: 24 per support DoF */
   double bytes_fp32;          /* same for FP32: 12 per support DoF */
@@ -200,6 +208,18 @@ int ghost_faces(const ghost_ctx *ctx, int axis, int32_t *out, int64_t cap);
  *   nodes, weights  k+1 GLL nodes and weights on [0, 1]
  */
 int ghost_tables(const ghost_ctx *ctx, double *jumps, double *mass, double *nodes, double *weights);
+
+/*
+ * Copy the owner-computes layout to HOST arrays (inspection and tests); each may be NULL to skip it.
+ *   boxes   10 int32 per box: lo[3], hi[3] (owned node ranges), first visit, visit count,
+ *           first flush run, flush-run count                       (capacity box_cap boxes)
+ *   visits  packed faces: c0 | c1 << 20 | c2 << 40 | axis << 60 | primary << 62  (visit_cap)
+ *   flush   3 int64 per run of owned support nodes: lattice start, length, accumulator offset
+ *                                                                       (capacity flush_cap runs)
+ * GHOST_EINVAL if a capacity is too small.
+ */
+int ghost_owner_layout(const ghost_ctx *ctx, int32_t *boxes, int64_t box_cap, uint64_t *visits,
+                       int64_t visit_cap, int64_t *flush, int64_t flush_cap);
 
 /* Release the context and every allocation it owns.  NULL is a no-op. */
 void ghost_destroy(ghost_ctx *ctx);

@@ -165,7 +165,9 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
   } else {
     return fail(GHOST_EINVAL, "unknown level-set kind %d", ls->kind);
   }
-  if (flags & ~(GHOST_FP64 | GHOST_FP32 | GHOST_COLOURED)) return fail(GHOST_EINVAL, "unknown flags");
+  if (flags & ~(GHOST_FP64 | GHOST_FP32 | GHOST_COLOURED | GHOST_ATOMIC)) return fail(GHOST_EINVAL, "unknown flags");
+  if ((flags & GHOST_COLOURED) && (flags & GHOST_ATOMIC))
+    return fail(GHOST_EINVAL, "GHOST_COLOURED and GHOST_ATOMIC are exclusive");
   if (device < -1) return fail(GHOST_EINVAL, "device must be >= -1");
 
   ghost_ctx *c = new (std::nothrow) ghost_ctx;
@@ -197,6 +199,11 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
     d.L[a] = p.L[a];
   }
   d.n_batches = (int)p.batches.size();
+  d.scatter = (flags & GHOST_COLOURED) ? ghost::Scatter::Coloured
+              : (flags & GHOST_ATOMIC) ? ghost::Scatter::Atomic : ghost::Scatter::Owner;
+  d.n_leaves = (int)p.leaves.size();
+  d.max_acc = p.max_acc;
+  d.max_lines = p.max_lines_box;
   d.coloured = p.coloured;
   d.n_colours = p.n_colours;
   d.colour_begin = p.colour_begin.empty() ? nullptr : p.colour_begin.data();
@@ -233,7 +240,20 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
     if (rc == GHOST_OK) rc = upload(c, p.cls.data(), p.cls.size(), const_cast<int8_t **>(&cl));
     if (rc == GHOST_OK) rc = upload(c, t64.data(), t64.size(), &d.tab64);
     if (rc == GHOST_OK) rc = upload(c, t32.data(), t32.size(), &d.tab32);
-    if (rc == GHOST_OK) rc = upload<double>(c, nullptr, (size_t)std::max(1, d.n_batches) * k, &d.vjp_partial);
+    const ghost::Leaf *lv = nullptr;
+    const ghost::Visit *vv = nullptr;
+    const ghost::FlushRec *fv = nullptr;
+    const ghost::LineRec *lr = nullptr;
+    if (rc == GHOST_OK) rc = upload(c, p.leaves.data(), p.leaves.size(), const_cast<ghost::Leaf **>(&lv));
+    if (rc == GHOST_OK) rc = upload(c, p.visits.data(), p.visits.size(), const_cast<ghost::Visit **>(&vv));
+    if (rc == GHOST_OK) rc = upload(c, p.flushes.data(), p.flushes.size(), const_cast<ghost::FlushRec **>(&fv));
+    if (rc == GHOST_OK) rc = upload(c, p.lines.data(), p.lines.size(), const_cast<ghost::LineRec **>(&lr));
+    if (rc == GHOST_OK)
+      rc = upload<double>(c, nullptr, (size_t)std::max(1, std::max(d.n_batches, d.n_leaves)) * k, &d.vjp_partial);
+    d.leaves = lv;
+    d.visits = vv;
+    d.flushes = fv;
+    d.lines = lr;
     if (rc != GHOST_OK) {
       std::string msg = g_error;
       free_device(c);
@@ -339,6 +359,10 @@ int ghost_info(const ghost_ctx *ctx, ghost_stats *out) {
   for (int a = 1; a < p.dim; ++a) tang *= K;
   out->n_patch_dofs = (2 * p.k + 1) * tang;
   out->n_batches = (int64_t)p.batches.size();
+  out->n_boxes = (int64_t)p.leaves.size();
+  out->n_visits = p.n_visits;
+  out->brick = p.brick;
+  out->max_acc = p.max_acc;
   out->flops_per_face = 2.0 * (2.0 * p.k * (2 * p.k + 1) * tang + (double)(p.dim - 1) * p.k * tang * K);
   out->bytes_fp64 = 24.0 * (double)p.n_support;
   out->bytes_fp32 = 12.0 * (double)p.n_support;
@@ -356,6 +380,37 @@ int ghost_faces(const ghost_ctx *ctx, int axis, int32_t *out, int64_t cap) {
     out[4 * f + 1] = fc[3 * f + 1];
     out[4 * f + 2] = fc[3 * f + 2];
     out[4 * f + 3] = ctx->plan.face_colour[axis][f];
+  }
+  return GHOST_OK;
+}
+
+int ghost_owner_layout(const ghost_ctx *ctx, int32_t *boxes, int64_t box_cap, uint64_t *visits,
+                       int64_t visit_cap, int64_t *flush, int64_t flush_cap) {
+  if (!ctx) return fail(GHOST_EINVAL, "null context");
+  const ghost::Plan &p = ctx->plan;
+  if (boxes) {
+    if (box_cap < (int64_t)p.leaves.size()) return fail(GHOST_EINVAL, "box capacity too small");
+    for (size_t i = 0; i < p.leaves.size(); ++i) {
+      const ghost::Leaf &l = p.leaves[i];
+      int32_t *o = boxes + 10 * i;
+      for (int a = 0; a < 3; ++a) { o[a] = l.lo[a]; o[3 + a] = l.hi[a]; }
+      o[6] = l.visit_first;
+      o[7] = l.visit_count;
+      o[8] = l.flush_first;
+      o[9] = l.flush_count;
+    }
+  }
+  if (visits) {
+    if (visit_cap < (int64_t)p.visits.size()) return fail(GHOST_EINVAL, "visit capacity too small");
+    std::memcpy(visits, p.visits.data(), p.visits.size() * sizeof(uint64_t));
+  }
+  if (flush) {
+    if (flush_cap < (int64_t)p.flushes.size()) return fail(GHOST_EINVAL, "flush capacity too small");
+    for (size_t i = 0; i < p.flushes.size(); ++i) {
+      flush[3 * i] = p.flushes[i].start;
+      flush[3 * i + 1] = p.flushes[i].len;
+      flush[3 * i + 2] = p.flushes[i].acc;
+    }
   }
   return GHOST_OK;
 }

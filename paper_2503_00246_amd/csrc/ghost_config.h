@@ -6,6 +6,9 @@ namespace ghost {
 constexpr int kMaxDegree = 7;
 constexpr int kBlockThreads = 256;
 
+// Owner-computes accumulator capacity (entries) of one workgroup's node box.
+constexpr int kDefaultAccCap = 3072;
+
 // Threads per face: one per tangential node line, (k+1)^(d-1).
 constexpr int lines_per_face(int dim, int k) { return dim == 3 ? (k + 1) * (k + 1) : (k + 1); }
 

@@ -21,8 +21,11 @@ inline int tab_gllw(int k) { return tab_hscale(k) + k; }
 inline int tab_size64(int k) { return tab_gllw(k) + k + 1; }
 inline int tab_size32(int k) { return tab_hscale(k); }
 
+enum class Scatter { Owner = 0, Atomic = 1, Coloured = 2 };
+
 struct DevPlan {
   int dim = 0, k = 0;
+  Scatter scatter = Scatter::Owner;
   int32_t stride[3] = {1, 1, 1};
   int n[3] = {1, 1, 1};
   int64_t L[3] = {1, 1, 1};
@@ -41,9 +44,17 @@ struct DevPlan {
   int n_active_runs = 0;
   const int8_t *cls = nullptr;        // device cell classes
 
+  // owner-computes layout
+  const Leaf *leaves = nullptr;
+  const Visit *visits = nullptr;
+  const FlushRec *flushes = nullptr;
+  const LineRec *lines = nullptr;
+  int n_leaves = 0;
+  int max_acc = 0, max_lines = 0;
+
   double *tab64 = nullptr;
   float *tab32 = nullptr;
-  double *vjp_partial = nullptr;      // n_batches * k doubles
+  double *vjp_partial = nullptr;      // max(n_batches, n_leaves) * k doubles
 };
 
 hipError_t launch_apply_f64(const DevPlan &p, const double *u, double *y, bool accumulate, hipStream_t s);

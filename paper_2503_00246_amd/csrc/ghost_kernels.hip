@@ -205,6 +205,215 @@ __global__ __launch_bounds__(kBlockThreads) void face_kernel(
   }
 }
 
+
+// Owner-computes apply.  Workgroup = one box of lattice nodes; it runs the same per-face pipeline
+// as face_kernel over every face whose patch meets the box (faces crossing the box boundary are
+// recomputed by each box they touch), keeps only the contributions to nodes inside the box,
+// sums them in an LDS accumulator, and finally writes each owned support node once with plain,
+// coalesced stores.  No global atomics, and y needs no prior zeroing.
+// VJP: x = w drives du; u2 = u gives the order-wise reduction, counted once per face (on the
+// face's primary visit).
+template <typename T, int D, int K, bool VJP>
+__global__ __launch_bounds__(kBlockThreads) void owner_kernel(
+    const T *__restrict__ x, const T *__restrict__ u2, T *__restrict__ y, double *__restrict__ partial,
+    const Leaf *__restrict__ leaves, const Visit *__restrict__ visits, const FlushRec *__restrict__ flushes,
+    const LineRec *__restrict__ lines, int acc_bytes, const T *__restrict__ tab, int s0, int s1, int s2,
+    int accumulate) {
+  constexpr int k = K - 1, NN = 2 * k + 1;
+  constexpr int TL = lines_per_face(D, k), FPB = faces_per_block(D, k), NT = TL * FPB;
+  __shared__ T sa[FPB * k * TL];
+  __shared__ T sb[FPB * k * TL];
+  extern __shared__ __align__(16) unsigned char dyn_smem[];
+  T *acc = reinterpret_cast<T *>(dyn_smem);
+  int *table = reinterpret_cast<int *>(dyn_smem + acc_bytes);
+  const T *g = tab;
+  const T *gs = tab + k * NN;
+  const T *M = tab + 2 * k * NN;
+
+  const int li = xcd_remap(blockIdx.x, gridDim.x);
+  const Leaf lf = leaves[li];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < lf.acc_size; i += kBlockThreads) acc[i] = T(0);
+  for (int i = tid; i < lf.line_count; i += kBlockThreads) {
+    const LineRec r = lines[lf.line_first + i];
+    table[r.line] = r.base;
+  }
+  const int f = tid / TL, t = tid - f * TL;
+  const bool in_block = tid < NT;
+  const int t1 = (D == 3) ? t % K : t;
+  const int t2 = (D == 3) ? t / K : 0;
+  const int w1 = lf.hi[1] - lf.lo[1];
+  double pj[k];
+#pragma unroll
+  for (int j = 0; j < k; ++j) pj[j] = 0.0;
+  __syncthreads();
+
+  for (int v0 = 0; v0 < lf.visit_count; v0 += FPB) {
+    const int vi = v0 + f;
+    const bool live = in_block && vi < lf.visit_count;
+    const Visit vis = live ? visits[lf.visit_first + vi] : Visit(0);
+    const int c0 = (int)(vis & 0xFFFFF), c1 = (int)((vis >> 20) & 0xFFFFF), c2 = (int)((vis >> 40) & 0xFFFFF);
+    const int axis = (int)((vis >> 60) & 3);
+    const bool prim = ((vis >> 62) & 1) != 0;
+    // normal axis n and tangential axes ta < tb, resolved with selects (no indexed local arrays)
+    const bool ax0 = axis == 0, ax1 = axis == 1, ax2 = axis == 2;
+    const int sn = ax0 ? s0 : (ax1 ? s1 : s2);
+    const int st1 = ax0 ? s1 : s0;
+    const int st2 = (D == 3) ? (ax2 ? s1 : s2) : 0;
+    const int64_t base = (int64_t)k * ((int64_t)c0 * s0 + (int64_t)c1 * s1 + (int64_t)c2 * s2) +
+                         (int64_t)(t1 * st1 + t2 * st2);
+
+    T a[k], au[k];
+#pragma unroll
+    for (int j = 0; j < k; ++j) a[j] = au[j] = T(0);
+    if (live) {
+      T line[NN];
+#pragma unroll
+      for (int i = 0; i < NN; ++i) line[i] = x[base + i * sn];
+#pragma unroll
+      for (int j = 0; j < k; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int i = 0; i < NN; ++i) s = fma(g[j * NN + i], line[i], s);
+        a[j] = s;
+      }
+      if (VJP && prim) {
+#pragma unroll
+        for (int i = 0; i < NN; ++i) line[i] = u2[base + i * sn];
+#pragma unroll
+        for (int j = 0; j < k; ++j) {
+          T s = T(0);
+#pragma unroll
+          for (int i = 0; i < NN; ++i) s = fma(g[j * NN + i], line[i], s);
+          au[j] = s;
+        }
+      }
+    }
+    if (in_block) {
+#pragma unroll
+      for (int j = 0; j < k; ++j) sa[(f * k + j) * TL + t] = a[j];
+    }
+    __syncthreads();
+    const T *res;
+    if (D == 3) {
+      if (in_block && t1 < k) {
+        const T *row = &sa[(f * k + t1) * TL + t2 * K];
+        T r[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m) r[m] = row[m];
+        T *out = &sb[(f * k + t1) * TL + t2 * K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          T s = T(0);
+#pragma unroll
+          for (int m = 0; m < K; ++m) s = fma(M[q * K + m], r[m], s);
+          out[q] = s;
+        }
+      }
+      __syncthreads();
+      if (in_block && t2 < k) {
+        const T *col = &sb[(f * k + t2) * TL + t1];
+        T r[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m) r[m] = col[m * K];
+        T *out = &sa[(f * k + t2) * TL + t1];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          T s = T(0);
+#pragma unroll
+          for (int m = 0; m < K; ++m) s = fma(M[q * K + m], r[m], s);
+          out[q * K] = s;
+        }
+      }
+      __syncthreads();
+      res = sa;
+    } else {
+      if (in_block && t < k) {
+        const T *row = &sa[(f * k + t) * TL];
+        T r[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m) r[m] = row[m];
+        T *out = &sb[(f * k + t) * TL];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          T s = T(0);
+#pragma unroll
+          for (int m = 0; m < K; ++m) s = fma(M[q * K + m], r[m], s);
+          out[q] = s;
+        }
+      }
+      __syncthreads();
+      res = sb;
+    }
+    T cj[k];
+#pragma unroll
+    for (int j = 0; j < k; ++j) cj[j] = in_block ? res[(f * k + j) * TL + t] : T(0);
+    if (live) {
+      // node coordinates: along the normal n0 + i, along the tangential axes ia, ib (fixed per thread)
+      const int n0 = k * (ax0 ? c0 : (ax1 ? c1 : c2));
+      const int ia = k * (ax0 ? c1 : c0) + t1;
+      const int ib = (D == 3) ? k * (ax2 ? c1 : c2) + t2 : 0;
+      const int lo_n = ax0 ? lf.lo[0] : (ax1 ? lf.lo[1] : lf.lo[2]);
+      const int hi_n = ax0 ? lf.hi[0] : (ax1 ? lf.hi[1] : lf.hi[2]);
+      const int lo_a = ax0 ? lf.lo[1] : lf.lo[0], hi_a = ax0 ? lf.hi[1] : lf.hi[0];
+      const int lo_b = ax2 ? lf.lo[1] : lf.lo[2], hi_b = ax2 ? lf.hi[1] : lf.hi[2];
+      bool own_t = ia >= lo_a && ia < hi_a;
+      if (D == 3) own_t = own_t && ib >= lo_b && ib < hi_b;
+      if (own_t) {
+#pragma unroll
+        for (int i = 0; i < NN; ++i) {
+          const int in = n0 + i;
+          if (in >= lo_n && in < hi_n) {
+            T s = T(0);
+#pragma unroll
+            for (int j = 0; j < k; ++j) s = fma(gs[j * NN + i], cj[j], s);
+            const int x0 = ax0 ? in : ia;
+            const int x1 = ax1 ? in : (ax0 ? ia : ib);
+            const int x2 = (D == 3) ? (ax2 ? in : ib) : 0;
+            const int ln = (x1 - lf.lo[1]) + w1 * (x2 - lf.lo[2]);
+            __hip_atomic_fetch_add(&acc[table[ln] + x0], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+      }
+      if (VJP && prim) {
+#pragma unroll
+        for (int j = 0; j < k; ++j) pj[j] += (double)au[j] * (double)cj[j];
+      }
+    }
+    __syncthreads();  // sa / sb are reused by the next batch
+  }
+
+  // flush: 8 lanes per run of owned support nodes
+  const int sub = tid >> 3, sl = tid & 7;
+  for (int r = sub; r < lf.flush_count; r += kBlockThreads / 8) {
+    const FlushRec fr = flushes[lf.flush_first + r];
+    for (int i = sl; i < fr.len; i += 8) {
+      const T v = acc[fr.acc + i];
+      T *p = y + fr.start + i;
+      *p = accumulate ? *p + v : v;
+    }
+  }
+
+  if (VJP) {
+    __shared__ double red[kBlockThreads / 64][k];
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int j = 0; j < k; ++j) {
+      double v = pj[j];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) red[wave][j] = v;
+    }
+    __syncthreads();
+    if (tid < k) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBlockThreads / 64; ++w) s += red[w][tid];
+      partial[(int64_t)li * k + tid] = s;
+    }
+  }
+}
+
 template <typename T>
 __global__ void zero_runs_kernel(T *__restrict__ y, const Run *__restrict__ runs, int n_runs) {
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
@@ -309,6 +518,28 @@ hipError_t dispatch(const DevPlan &p, const T *x, const T *u2, T *y, double *par
   return hipErrorInvalidValue;
 }
 
+
+template <typename T, bool VJP>
+hipError_t dispatch_owner(const DevPlan &p, const T *x, const T *u2, T *y, const T *tab, bool accumulate,
+                          hipStream_t s) {
+  if (p.n_leaves <= 0) return hipSuccess;
+  const int acc_bytes = ((p.max_acc * (int)sizeof(T)) + 15) / 16 * 16;
+  const size_t shmem = (size_t)acc_bytes + (size_t)p.max_lines * sizeof(int);
+  const dim3 grid(p.n_leaves), block(kBlockThreads);
+#define GHOST_OCASE(D_, K_)                                                                                     \
+  if (p.dim == D_ && p.k + 1 == K_) {                                                                          \
+    hipLaunchKernelGGL((owner_kernel<T, D_, K_, VJP>), grid, block, shmem, s, x, u2, y, p.vjp_partial, p.leaves, \
+                       p.visits, p.flushes, p.lines, acc_bytes, tab, p.stride[0], p.stride[1], p.stride[2],   \
+                       (int)accumulate);                                                                        \
+    return hipGetLastError();                                                                                   \
+  }
+  GHOST_OCASE(2, 2) GHOST_OCASE(2, 3) GHOST_OCASE(2, 4) GHOST_OCASE(2, 5) GHOST_OCASE(2, 6) GHOST_OCASE(2, 7)
+  GHOST_OCASE(2, 8) GHOST_OCASE(3, 2) GHOST_OCASE(3, 3) GHOST_OCASE(3, 4) GHOST_OCASE(3, 5) GHOST_OCASE(3, 6)
+  GHOST_OCASE(3, 7) GHOST_OCASE(3, 8)
+#undef GHOST_OCASE
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t zero_support(const DevPlan &p, T *y, hipStream_t s) {
   if (p.n_support_runs == 0) return hipSuccess;
@@ -321,7 +552,7 @@ hipError_t zero_support(const DevPlan &p, T *y, hipStream_t s) {
 
 template <typename T, bool VJP>
 hipError_t run_faces(const DevPlan &p, const T *x, const T *u2, T *y, const T *tab, hipStream_t s) {
-  if (!p.coloured) return dispatch<T, true, VJP>(p, x, u2, y, p.vjp_partial, tab, 0, p.n_batches, s);
+  if (p.scatter == Scatter::Atomic) return dispatch<T, true, VJP>(p, x, u2, y, p.vjp_partial, tab, 0, p.n_batches, s);
   for (int c = 0; c < p.n_colours; ++c) {
     hipError_t e = dispatch<T, false, VJP>(p, x, u2, y, p.vjp_partial, tab, p.colour_begin[c],
                                            p.colour_begin[c + 1] - p.colour_begin[c], s);
@@ -333,6 +564,7 @@ hipError_t run_faces(const DevPlan &p, const T *x, const T *u2, T *y, const T *t
 }  // namespace
 
 hipError_t launch_apply_f64(const DevPlan &p, const double *u, double *y, bool accumulate, hipStream_t s) {
+  if (p.scatter == Scatter::Owner) return dispatch_owner<double, false>(p, u, nullptr, y, p.tab64, accumulate, s);
   if (!accumulate) {
     hipError_t e = zero_support(p, y, s);
     if (e != hipSuccess) return e;
@@ -341,6 +573,7 @@ hipError_t launch_apply_f64(const DevPlan &p, const double *u, double *y, bool a
 }
 
 hipError_t launch_apply_f32(const DevPlan &p, const float *u, float *y, bool accumulate, hipStream_t s) {
+  if (p.scatter == Scatter::Owner) return dispatch_owner<float, false>(p, u, nullptr, y, p.tab32, accumulate, s);
   if (!accumulate) {
     hipError_t e = zero_support(p, y, s);
     if (e != hipSuccess) return e;
@@ -350,17 +583,21 @@ hipError_t launch_apply_f32(const DevPlan &p, const float *u, float *y, bool acc
 
 hipError_t launch_vjp(const DevPlan &p, const double *u, const double *w, double *du, double *dgamma,
                       bool accumulate, hipStream_t s) {
-  if (!accumulate) {
-    hipError_t e = zero_support(p, du, s);
-    if (e != hipSuccess) return e;
+  const bool owner = p.scatter == Scatter::Owner;
+  const int n_parts = owner ? p.n_leaves : p.n_batches;
+  hipError_t e = hipSuccess;
+  if (owner) {
+    e = dispatch_owner<double, true>(p, w, u, du, p.tab64, accumulate, s);
+  } else {
+    if (!accumulate) e = zero_support(p, du, s);
+    if (e == hipSuccess) e = run_faces<double, true>(p, w, u, du, p.tab64, s);
   }
-  hipError_t e = run_faces<double, true>(p, w, u, du, p.tab64, s);
   if (e != hipSuccess) return e;
-  if (p.n_batches == 0) {
+  if (n_parts == 0) {
     hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, dgamma, (int64_t)p.k, 0.0);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(vjp_reduce_kernel, dim3(p.k), dim3(kBlockThreads), 0, s, p.vjp_partial, p.n_batches,
+  hipLaunchKernelGGL(vjp_reduce_kernel, dim3(p.k), dim3(kBlockThreads), 0, s, p.vjp_partial, n_parts,
                      p.k, p.tab64 + tab_hscale(p.k), dgamma);
   return hipGetLastError();
 }

@@ -29,8 +29,10 @@ class GhostOperator:
     host-only plan (inspection without a GPU).
     """
 
+    SCATTERS = ("owner", "atomic", "coloured")
+
     def __init__(self, d, n, lo, h, k, gamma, centre=None, radius=None, cell_class=None,
-                 coloured=False, device=0):
+                 scatter="owner", device=0):
         lib = L.load()
         mesh = L.GhostMesh()
         mesh.dim = d
@@ -51,7 +53,11 @@ class GhostOperator:
                 ls.centre[a] = float(centre[a]) if a < d else 0.0
             ls.radius = float(radius)
         g = (ctypes.c_double * k)(*[float(x) for x in gamma])
-        flags = L.GHOST_FP64 | L.GHOST_FP32 | (L.GHOST_COLOURED if coloured else 0)
+        if scatter not in self.SCATTERS:
+            raise ValueError(f"scatter must be one of {self.SCATTERS}")
+        flags = L.GHOST_FP64 | L.GHOST_FP32 | {"owner": 0, "atomic": L.GHOST_ATOMIC,
+                                               "coloured": L.GHOST_COLOURED}[scatter]
+        self.scatter = scatter
         handle = ctypes.c_void_p()
         L.check(lib.ghost_setup(ctypes.byref(mesh), ctypes.byref(ls), int(k), g, flags, int(device),
                                 ctypes.byref(handle)))
@@ -65,9 +71,9 @@ class GhostOperator:
         self.n_lattice = self.stats["n_lattice"]
 
     @classmethod
-    def from_workload(cls, w, coloured=False, device=0, gamma=None):
+    def from_workload(cls, w, scatter="owner", device=0, gamma=None):
         return cls(w.d, w.n, w.lo, w.h, w.k, w.gamma() if gamma is None else gamma,
-                   centre=w.centre, radius=w.radius, coloured=coloured, device=device)
+                   centre=w.centre, radius=w.radius, scatter=scatter, device=device)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -174,6 +180,21 @@ class GhostOperator:
         out = np.zeros((max(nf, 1), 4), dtype=np.int32)
         L.check(self._lib.ghost_faces(self._h, axis, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nf))
         return out[:nf]
+
+    def owner_layout(self):
+        """Owner-computes layout: (boxes (nb, 10) int32, visits uint64, flush (nr, 3) int64)."""
+        nb, nv = self.stats["n_boxes"], self.stats["n_visits"]
+        boxes = np.zeros((max(nb, 1), 10), dtype=np.int32)
+        visits = np.zeros(max(nv, 1), dtype=np.uint64)
+        L.check(self._lib.ghost_owner_layout(self._h, boxes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nb,
+                                             visits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nv, None, 0))
+        boxes = boxes[:nb]
+        nr = int(boxes[:, 8].max() + boxes[:, 9][boxes[:, 8].argmax()]) if nb else 0
+        nr = int((boxes[:, 8] + boxes[:, 9]).max()) if nb else 0
+        flush = np.zeros((max(nr, 1), 3), dtype=np.int64)
+        L.check(self._lib.ghost_owner_layout(self._h, None, 0, None, 0,
+                                             flush.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nr))
+        return boxes, visits[:nv], flush[:nr]
 
     def tables(self):
         k = self.k

@@ -31,9 +31,12 @@ def nerr(y, ref):
     return float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
 
 
-def gpu_op(w, coloured=False):
+SCATTERS = ("owner", "atomic", "coloured")
+
+
+def gpu_op(w, scatter="owner"):
     from paper_2503_00246_amd.operator import GhostOperator
-    return GhostOperator.from_workload(w, coloured=coloured)
+    return GhostOperator.from_workload(w, scatter=scatter)
 
 
 def small(d, k, n, name=None, centre=None, radius=0.73):
@@ -41,12 +44,12 @@ def small(d, k, n, name=None, centre=None, radius=0.73):
     return Workload(name or f"small_d{d}_k{k}_n{n}", d, k, (n,) * d, (-1.0,) * d, centre, radius)
 
 
-@pytest.mark.parametrize("coloured", [False, True])
+@pytest.mark.parametrize("scatter", SCATTERS)
 @pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64"])
-def test_apply_fp64_full_parity(name, coloured):
+def test_apply_fp64_full_parity(name, scatter):
     w = WORKLOADS[name]
     o = oracle_for(w)
-    op = gpu_op(w, coloured)
+    op = gpu_op(w, scatter)
     u = uniform_vector(w.n_lattice, SEED_U)
     ref = o.apply(u)
     ut = torch.from_numpy(u).cuda()
@@ -67,11 +70,12 @@ def test_apply_fp64_full_parity(name, coloured):
     assert nerr(y3[sup], ref[sup]) <= TOL64 and np.all(y3[off] == 3.0)
 
 
+@pytest.mark.parametrize("scatter", SCATTERS)
 @pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64"])
-def test_apply_fp32_parity(name):
+def test_apply_fp32_parity(name, scatter):
     w = WORKLOADS[name]
     o = oracle_for(w)
-    op = gpu_op(w)
+    op = gpu_op(w, scatter)
     u = uniform_vector(w.n_lattice, SEED_U)
     ref = o.apply(u.astype(np.float32).astype(np.float64))
     y = op.apply_f32(torch.from_numpy(u.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
@@ -91,12 +95,13 @@ def test_apply_all_degrees(d, k, n):
     ref = o.apply(u)
     sup = o.support()
     ut = torch.from_numpy(u).cuda()
-    for coloured in (False, True):
-        y = gpu_op(w, coloured).apply(ut).cpu().numpy()
-        assert nerr(y[sup], ref[sup]) <= TOL64, (coloured,)
-    y32 = op.apply_f32(ut.float()).cpu().numpy().astype(np.float64)
     ref32 = o.apply(u.astype(np.float32).astype(np.float64))
-    assert nerr(y32[sup], ref32[sup]) <= TOL32
+    for scatter in SCATTERS:
+        ops = gpu_op(w, scatter)
+        y = ops.apply(ut).cpu().numpy()
+        assert nerr(y[sup], ref[sup]) <= TOL64, scatter
+        y32 = ops.apply_f32(ut.float()).cpu().numpy().astype(np.float64)
+        assert nerr(y32[sup], ref32[sup]) <= TOL32, scatter
 
 
 def _node_coords(w):
@@ -133,9 +138,11 @@ def test_null_space_and_symmetry_on_gpu():
     assert abs(a_ - b_) <= 1e-12 * abs(a_)
 
 
-def test_zero_faces_is_noop():
+@pytest.mark.parametrize("scatter", SCATTERS)
+def test_zero_faces_is_noop(scatter):
     from paper_2503_00246_amd.operator import GhostOperator
-    op = GhostOperator(3, (8, 8, 8), (-1, -1, -1), 0.25, 3, [1.0, 1.0, 1.0], centre=(9.0, 9.0, 9.0), radius=0.5)
+    op = GhostOperator(3, (8, 8, 8), (-1, -1, -1), 0.25, 3, [1.0, 1.0, 1.0], centre=(9.0, 9.0, 9.0), radius=0.5,
+                       scatter=scatter)
     assert op.stats["n_faces_total"] == 0
     u = torch.ones(op.n_lattice, dtype=torch.float64, device="cuda")
     y = torch.full_like(u, 2.0)

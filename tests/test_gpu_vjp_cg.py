@@ -22,7 +22,8 @@ def oracle(w, per_face=False):
     return GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), centre=w.centre, radius=w.radius, per_face=per_face)
 
 
-def test_vjp_matches_oracle_gradient_on_submesh():
+@pytest.mark.parametrize("scatter", ["owner", "atomic", "coloured"])
+def test_vjp_matches_oracle_gradient_on_submesh(scatter):
     """16^3 block of the 96^3 Q4 mesh: the oracle's exact sparse gradients of L = 0.5|G u - t|^2."""
     w = submesh_q4_16()
     o = oracle(w)
@@ -30,7 +31,7 @@ def test_vjp_matches_oracle_gradient_on_submesh():
     u = uniform_vector(w.n_lattice, SEED_U)
     t = uniform_vector(w.n_lattice, SEED_T)
     _, du_ref, dg_ref = o.gradients(u, t)
-    op = gpu_op(w)
+    op = gpu_op(w, scatter=scatter)
     ut, tt = torch.from_numpy(u).cuda(), torch.from_numpy(t).cuda()
     r = op.apply(ut) - tt
     du, dg = op.vjp(ut, r)

@@ -35,8 +35,8 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, name)
 
 
-def _host(w, coloured=False, **kw):
-    return GhostOperator.from_workload(w, coloured=coloured, device=-1, **kw)
+def _host(w, scatter="owner", **kw):
+    return GhostOperator.from_workload(w, scatter=scatter, device=-1, **kw)
 
 
 @pytest.mark.parametrize("k", range(1, 8))
@@ -91,7 +91,7 @@ def test_flop_count_formula():
 def test_colouring_is_race_free(name):
     """No two faces of one colour share a lattice node (exact check with the oracle's patch numbering)."""
     w = WORKLOADS[name]
-    op = _host(w, coloured=True)
+    op = _host(w, scatter="coloured")
     per_axis = 3 * 2 ** (w.d - 1)
     assert op.stats["n_colours"] == w.d * per_axis
     owner = {}
@@ -182,3 +182,65 @@ def test_host_only_context_refuses_device_work(lib):
     assert lib.ghost_faces(op._h, 0, small.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 1) == L.GHOST_EINVAL
     assert lib.ghost_faces(op._h, 5, small.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 1) == L.GHOST_EINVAL
     lib.ghost_destroy(None)  # no-op
+
+
+@pytest.mark.parametrize("name,brick", [("disk2d_q2_32", None), ("ball3d_q3_64", None), ("ball3d_q3_64", "3"),
+                                        ("ball3d_q3_64", "5")])
+def test_owner_layout_partitions_support(name, brick, monkeypatch):
+    """Owner-computes layout: the flush runs partition the support exactly, every run lies in its
+    box, accumulator offsets of a box are disjoint, each box visits exactly the faces whose patch
+    meets it, and every face has exactly one primary visit (the box holding its first patch node)."""
+    cap = 6144
+    if brick:
+        cap = 700
+        monkeypatch.setenv("GHOST_BRICK", brick)
+        monkeypatch.setenv("GHOST_ACC_CAP", str(cap))  # force splitting
+    w = WORKLOADS[name]
+    op = _host(w)
+    boxes, visits, flush = op.owner_layout()
+    assert op.stats["n_visits"] == len(visits) and 0 < op.stats["max_acc"] <= cap
+    L_ = np.array(list(w.lattice) + [1] * (3 - w.d))
+    cls = omesh.classify_ball(w.n, w.lo, w.h, w.centre, w.radius)
+    faces = omesh.ghost_faces(cls)
+    sup = np.unique(np.concatenate([omesh.patch_dofs(faces[a], w.k, a, w.lattice).ravel() for a in range(w.d)]))
+    covered = np.concatenate([np.arange(s_, s_ + n_) for s_, n_, _ in flush])
+    assert len(covered) == len(sup) and np.array_equal(np.sort(covered), sup)
+    lo, hi = boxes[:, 0:3].astype(np.int64), boxes[:, 3:6].astype(np.int64)
+    # runs inside their box, accumulator offsets disjoint per box
+    box_of_run = np.repeat(np.arange(len(boxes)), boxes[:, 9])
+    order = np.concatenate([np.arange(b[8], b[8] + b[9]) for b in boxes])
+    runs = flush[order]
+    I = np.stack([runs[:, 0] % L_[0], (runs[:, 0] // L_[0]) % L_[1], runs[:, 0] // (L_[0] * L_[1])], -1)
+    assert np.all(I >= lo[box_of_run]) and np.all(I < hi[box_of_run])
+    assert np.all(I[:, 0] + runs[:, 1] <= hi[box_of_run, 0])
+    for b in range(len(boxes)):
+        r = runs[box_of_run == b]
+        accs = np.concatenate([np.arange(a_, a_ + n_) for _, n_, a_ in r])
+        assert len(np.unique(accs)) == len(accs) and accs.min() >= 0
+    # visits: decode, compare with the boxes each face's patch meets
+    v = visits.astype(np.uint64)
+    c = np.stack([(v & 0xFFFFF), (v >> 20) & 0xFFFFF, (v >> 40) & 0xFFFFF], -1).astype(np.int64)
+    ax = ((v >> 60) & 3).astype(np.int64)
+    prim = ((v >> 62) & 1).astype(bool)
+    box_of_visit = np.repeat(np.arange(len(boxes)), boxes[:, 7])
+    order = np.concatenate([np.arange(b[6], b[6] + b[7]) for b in boxes])
+    c, ax, prim = c[order], ax[order], prim[order]
+    key_dims = np.array([1, 1 << 21, 1 << 42])
+    got = np.unique(np.stack([box_of_visit, ax, c @ key_dims], -1), axis=0)
+    want = []
+    for a in range(w.d):
+        f = np.concatenate([faces[a], np.zeros((len(faces[a]), 3 - w.d), dtype=np.int64)], 1)
+        plo = w.k * f
+        ext = np.array([2 * w.k + 1 if t == a else (w.k + 1 if t < w.d else 1) for t in range(3)])
+        phi = plo + ext
+        hit = np.all((plo[:, None, :] < hi[None]) & (phi[:, None, :] > lo[None]), axis=-1)  # (nf, nb)
+        fi, bi = np.nonzero(hit)
+        want.append(np.stack([bi, np.full(len(bi), a), f[fi] @ key_dims], -1))
+    want = np.unique(np.concatenate(want), axis=0)
+    assert np.array_equal(got, want)
+    # one primary visit per face, in the box holding the patch's first node
+    pk = np.unique(np.stack([ax[prim], c[prim] @ key_dims], -1), axis=0)
+    assert len(pk) == prim.sum() == sum(len(faces[a]) for a in range(w.d))
+    first = w.k * c[prim]
+    bprim = box_of_visit[prim]
+    assert np.all(first >= lo[bprim]) and np.all(first < hi[bprim])
