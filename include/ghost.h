@@ -64,9 +64,11 @@ extern "C" {
 #define GHOST_FP32 2u
 #define GHOST_COLOURED 4u /* scatter strategy: face-parallel, plain read-modify-write per race-free colour */
 #define GHOST_ATOMIC 8u   /* scatter strategy: face-parallel, hardware FP64/FP32 atomics */
-/* With neither flag the default owner-computes scatter is used: each workgroup owns a box of
- * lattice nodes, applies every face whose patch meets the box, accumulates in LDS and writes each
- * owned node once (no atomics, deterministic). */
+/* With neither flag the default box scatter is used: the cells are cut into bricks; a workgroup
+ * applies every face with a cell in its brick (expanding only into the brick's cells), sums the
+ * contributions over the brick's node box in LDS, writes nodes no other box contains straight to y
+ * and passes nodes on shared box faces through halo slots that a second kernel adds into y.  No
+ * global atomics; y needs no prior zeroing. */
 
 typedef struct ghost_ctx ghost_ctx;
 
@@ -97,10 +99,11 @@ typedef struct {
   int64_t n_faces_total;
   int64_t n_patch_dofs;       /* (2k+1)(k+1)^(d-1) nodes per face patch */
   int64_t n_batches;          /* workgroups of one face-parallel launch */
-  int64_t n_boxes;            /* owner-computes: node boxes (workgroups of one launch) */
-  int64_t n_visits;           /* owner-computes: face visits (>= n_faces_total; faces crossing boxes repeat) */
-  int brick;                  /* owner-computes: box edge in cells before splitting */
-  int max_acc;                /* owner-computes: largest LDS accumulator (entries) */
+  int64_t n_boxes;            /* box scatter: bricks with faces (workgroups of one launch) */
+  int64_t n_visits;           /* box scatter: face visits (faces split between bricks count twice) */
+  int64_t n_halo_slots;       /* box scatter: halo slots (values passed between the two kernels) */
+  int64_t n_halo_nodes;       /* box scatter: support nodes on shared box faces */
+  int brick;                  /* box scatter: brick edge in cells */
   double flops_per_face;      /* arithmetic of one face in the kernel, 2 per FMA */
   double bytes_fp64;          /* compulsory bytes of an accumulating FP64 apply: 24 per support DoF */
   double bytes_fp32;          /* same for FP32: 12 per support DoF */
@@ -210,16 +213,17 @@ int ghost_faces(const ghost_ctx *ctx, int axis, int32_t *out, int64_t cap);
 int ghost_tables(const ghost_ctx *ctx, double *jumps, double *mass, double *nodes, double *weights);
 
 /*
- * Copy the owner-computes layout to HOST arrays (inspection and tests); each may be NULL to skip it.
- *   boxes   10 int32 per box: lo[3], hi[3] (owned node ranges), first visit, visit count,
- *           first flush run, flush-run count                       (capacity box_cap boxes)
- *   visits  packed faces: c0 | c1 << 20 | c2 << 40 | axis << 60 | primary << 62  (visit_cap)
- *   flush   3 int64 per run of owned support nodes: lattice start, length, accumulator offset
- *                                                                       (capacity flush_cap runs)
+ * Copy the box-scatter layout to HOST arrays (inspection and tests); each may be NULL to skip it.
+ *   boxes   7 int32 per brick: node origin[3], first visit, visit count, first run, run count
+ *                                                                         (capacity box_cap boxes)
+ *   visits  packed faces: c0 | c1 << 20 | c2 << 40 | axis << 60 | half << 62, half 0 = whole patch,
+ *           1 = lower cell only (patch planes 0..k), 2 = upper cell only (planes k+1..2k)  (visit_cap)
+ *   runs    4 int64 per run of box nodes: lattice start, accumulator index, length, halo slot
+ *           (-1 = written to y)                                           (capacity run_cap runs)
  * GHOST_EINVAL if a capacity is too small.
  */
-int ghost_owner_layout(const ghost_ctx *ctx, int32_t *boxes, int64_t box_cap, uint64_t *visits,
-                       int64_t visit_cap, int64_t *flush, int64_t flush_cap);
+int ghost_box_layout(const ghost_ctx *ctx, int32_t *boxes, int64_t box_cap, uint64_t *visits,
+                     int64_t visit_cap, int64_t *runs, int64_t run_cap);
 
 /* Release the context and every allocation it owns.  NULL is a no-op. */
 void ghost_destroy(ghost_ctx *ctx);

@@ -16,7 +16,7 @@ GHOST_FP64, GHOST_FP32, GHOST_COLOURED, GHOST_ATOMIC = 1, 2, 4, 8
 GHOST_CG_FP64, GHOST_CG_MIXED = 0, 1
 
 EXPORTS = ["ghost_setup", "ghost_set_gamma", "ghost_apply", "ghost_apply_f32", "ghost_vjp",
-           "ghost_mass_diag", "ghost_cg", "ghost_info", "ghost_faces", "ghost_tables", "ghost_owner_layout",
+           "ghost_mass_diag", "ghost_cg", "ghost_info", "ghost_faces", "ghost_tables", "ghost_box_layout",
            "ghost_destroy", "ghost_last_error"]
 
 
@@ -37,8 +37,8 @@ class GhostStats(ctypes.Structure):
                 ("n_active_dofs", ctypes.c_int64), ("n_support_dofs", ctypes.c_int64),
                 ("n_faces", ctypes.c_int64 * 3), ("n_faces_total", ctypes.c_int64),
                 ("n_patch_dofs", ctypes.c_int64), ("n_batches", ctypes.c_int64),
-                ("n_boxes", ctypes.c_int64), ("n_visits", ctypes.c_int64), ("brick", ctypes.c_int),
-                ("max_acc", ctypes.c_int),
+                ("n_boxes", ctypes.c_int64), ("n_visits", ctypes.c_int64), ("n_halo_slots", ctypes.c_int64),
+                ("n_halo_nodes", ctypes.c_int64), ("brick", ctypes.c_int),
                 ("flops_per_face", ctypes.c_double), ("bytes_fp64", ctypes.c_double),
                 ("bytes_fp32", ctypes.c_double)]
 
@@ -90,8 +90,8 @@ def load(path=LIB_PATH):
     lib.ghost_info.argtypes = [P, ctypes.POINTER(GhostStats)]
     lib.ghost_faces.argtypes = [P, c_int, ctypes.POINTER(ctypes.c_int32), c_i64]
     lib.ghost_tables.argtypes = [P] + [ctypes.POINTER(ctypes.c_double)] * 4
-    lib.ghost_owner_layout.argtypes = [P, ctypes.POINTER(ctypes.c_int32), c_i64, ctypes.POINTER(ctypes.c_uint64),
-                                       c_i64, ctypes.POINTER(ctypes.c_int64), c_i64]
+    lib.ghost_box_layout.argtypes = [P, ctypes.POINTER(ctypes.c_int32), c_i64, ctypes.POINTER(ctypes.c_uint64),
+                                     c_i64, ctypes.POINTER(ctypes.c_int64), c_i64]
     lib.ghost_destroy.argtypes = [P]
     lib.ghost_destroy.restype = None
     lib.ghost_last_error.restype = ctypes.c_char_p

@@ -201,9 +201,8 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
   d.n_batches = (int)p.batches.size();
   d.scatter = (flags & GHOST_COLOURED) ? ghost::Scatter::Coloured
               : (flags & GHOST_ATOMIC) ? ghost::Scatter::Atomic : ghost::Scatter::Owner;
-  d.n_leaves = (int)p.leaves.size();
-  d.max_acc = p.max_acc;
-  d.max_lines = p.max_lines_box;
+  d.n_boxes = (int)p.boxes.size();
+  d.n_halo = (int)p.halo_node.size();
   d.coloured = p.coloured;
   d.n_colours = p.n_colours;
   d.colour_begin = p.colour_begin.empty() ? nullptr : p.colour_begin.data();
@@ -240,27 +239,28 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
     if (rc == GHOST_OK) rc = upload(c, p.cls.data(), p.cls.size(), const_cast<int8_t **>(&cl));
     if (rc == GHOST_OK) rc = upload(c, t64.data(), t64.size(), &d.tab64);
     if (rc == GHOST_OK) rc = upload(c, t32.data(), t32.size(), &d.tab32);
-    const ghost::Leaf *lv = nullptr;
+    const ghost::Box *bxv = nullptr;
     const ghost::Visit *vv = nullptr;
-    const ghost::FlushRec *fv = nullptr;
-    const ghost::LineRec *lr = nullptr;
-    if (rc == GHOST_OK) rc = upload(c, p.leaves.data(), p.leaves.size(), const_cast<ghost::Leaf **>(&lv));
+    const ghost::BoxLine *rv = nullptr;
+    const int64_t *hn = nullptr;
+    const int32_t *hp = nullptr, *hs = nullptr;
+    double *halo = nullptr;
+    if (rc == GHOST_OK) rc = upload(c, p.boxes.data(), p.boxes.size(), const_cast<ghost::Box **>(&bxv));
     if (rc == GHOST_OK) rc = upload(c, p.visits.data(), p.visits.size(), const_cast<ghost::Visit **>(&vv));
-    if (rc == GHOST_OK) rc = upload(c, p.flushes.data(), p.flushes.size(), const_cast<ghost::FlushRec **>(&fv));
-    if (rc == GHOST_OK) rc = upload(c, p.lines.data(), p.lines.size(), const_cast<ghost::LineRec **>(&lr));
+    if (rc == GHOST_OK) rc = upload(c, p.box_lines.data(), p.box_lines.size(), const_cast<ghost::BoxLine **>(&rv));
+    if (rc == GHOST_OK) rc = upload(c, p.halo_node.data(), p.halo_node.size(), const_cast<int64_t **>(&hn));
+    if (rc == GHOST_OK) rc = upload(c, p.halo_ptr.data(), p.halo_ptr.size(), const_cast<int32_t **>(&hp));
+    if (rc == GHOST_OK) rc = upload(c, p.halo_slot.data(), p.halo_slot.size(), const_cast<int32_t **>(&hs));
+    if (rc == GHOST_OK) rc = upload<double>(c, nullptr, (size_t)std::max<int64_t>(1, p.n_slots), &halo);
     if (rc == GHOST_OK)
-      rc = upload<double>(c, nullptr, (size_t)std::max(1, std::max(d.n_batches, d.n_leaves)) * k, &d.vjp_partial);
-    d.leaves = lv;
+      rc = upload<double>(c, nullptr, (size_t)std::max(1, std::max(d.n_batches, d.n_boxes)) * k, &d.vjp_partial);
+    d.boxes = bxv;
     d.visits = vv;
-    d.flushes = fv;
-    d.lines = lr;
-    if (rc != GHOST_OK) {
-      std::string msg = g_error;
-      free_device(c);
-      delete c;
-      g_error = msg;
-      return rc;
-    }
+    d.box_lines = rv;
+    d.halo_node = hn;
+    d.halo_ptr = hp;
+    d.halo_slot = hs;
+    d.halo = halo;
     d.face_base = fb;
     d.batches = bt;
     d.support_runs = sr;
@@ -359,10 +359,11 @@ int ghost_info(const ghost_ctx *ctx, ghost_stats *out) {
   for (int a = 1; a < p.dim; ++a) tang *= K;
   out->n_patch_dofs = (2 * p.k + 1) * tang;
   out->n_batches = (int64_t)p.batches.size();
-  out->n_boxes = (int64_t)p.leaves.size();
+  out->n_boxes = (int64_t)p.boxes.size();
   out->n_visits = p.n_visits;
   out->brick = p.brick;
-  out->max_acc = p.max_acc;
+  out->n_halo_slots = p.n_slots;
+  out->n_halo_nodes = (int64_t)p.halo_node.size();
   out->flops_per_face = 2.0 * (2.0 * p.k * (2 * p.k + 1) * tang + (double)(p.dim - 1) * p.k * tang * K);
   out->bytes_fp64 = 24.0 * (double)p.n_support;
   out->bytes_fp32 = 12.0 * (double)p.n_support;
@@ -384,32 +385,33 @@ int ghost_faces(const ghost_ctx *ctx, int axis, int32_t *out, int64_t cap) {
   return GHOST_OK;
 }
 
-int ghost_owner_layout(const ghost_ctx *ctx, int32_t *boxes, int64_t box_cap, uint64_t *visits,
-                       int64_t visit_cap, int64_t *flush, int64_t flush_cap) {
+int ghost_box_layout(const ghost_ctx *ctx, int32_t *boxes, int64_t box_cap, uint64_t *visits, int64_t visit_cap,
+                     int64_t *runs, int64_t run_cap) {
   if (!ctx) return fail(GHOST_EINVAL, "null context");
   const ghost::Plan &p = ctx->plan;
   if (boxes) {
-    if (box_cap < (int64_t)p.leaves.size()) return fail(GHOST_EINVAL, "box capacity too small");
-    for (size_t i = 0; i < p.leaves.size(); ++i) {
-      const ghost::Leaf &l = p.leaves[i];
-      int32_t *o = boxes + 10 * i;
-      for (int a = 0; a < 3; ++a) { o[a] = l.lo[a]; o[3 + a] = l.hi[a]; }
-      o[6] = l.visit_first;
-      o[7] = l.visit_count;
-      o[8] = l.flush_first;
-      o[9] = l.flush_count;
+    if (box_cap < (int64_t)p.boxes.size()) return fail(GHOST_EINVAL, "box capacity too small");
+    for (size_t i = 0; i < p.boxes.size(); ++i) {
+      const ghost::Box &b = p.boxes[i];
+      int32_t *o = boxes + 7 * i;
+      for (int a = 0; a < 3; ++a) o[a] = b.org[a];
+      o[3] = b.visit_first;
+      o[4] = b.visit_count;
+      o[5] = b.run_first;
+      o[6] = b.run_count;
     }
   }
   if (visits) {
     if (visit_cap < (int64_t)p.visits.size()) return fail(GHOST_EINVAL, "visit capacity too small");
     std::memcpy(visits, p.visits.data(), p.visits.size() * sizeof(uint64_t));
   }
-  if (flush) {
-    if (flush_cap < (int64_t)p.flushes.size()) return fail(GHOST_EINVAL, "flush capacity too small");
-    for (size_t i = 0; i < p.flushes.size(); ++i) {
-      flush[3 * i] = p.flushes[i].start;
-      flush[3 * i + 1] = p.flushes[i].len;
-      flush[3 * i + 2] = p.flushes[i].acc;
+  if (runs) {
+    if (run_cap < (int64_t)p.box_runs.size()) return fail(GHOST_EINVAL, "run capacity too small");
+    for (size_t i = 0; i < p.box_runs.size(); ++i) {
+      runs[4 * i] = p.box_runs[i].start;
+      runs[4 * i + 1] = p.box_runs[i].acc;
+      runs[4 * i + 2] = p.box_runs[i].len;
+      runs[4 * i + 3] = p.box_runs[i].slot;
     }
   }
   return GHOST_OK;

@@ -44,17 +44,20 @@ struct DevPlan {
   int n_active_runs = 0;
   const int8_t *cls = nullptr;        // device cell classes
 
-  // owner-computes layout
-  const Leaf *leaves = nullptr;
+  // box layout (default scatter)
+  const Box *boxes = nullptr;
   const Visit *visits = nullptr;
-  const FlushRec *flushes = nullptr;
-  const LineRec *lines = nullptr;
-  int n_leaves = 0;
-  int max_acc = 0, max_lines = 0;
+  const BoxLine *box_lines = nullptr;
+  int n_boxes = 0;
+  void *halo = nullptr;               // n_slots values of the apply's precision
+  const int64_t *halo_node = nullptr;
+  const int32_t *halo_ptr = nullptr;
+  const int32_t *halo_slot = nullptr;
+  int n_halo = 0;
 
   double *tab64 = nullptr;
   float *tab32 = nullptr;
-  double *vjp_partial = nullptr;      // max(n_batches, n_leaves) * k doubles
+  double *vjp_partial = nullptr;      // max(n_batches, n_boxes) * k doubles
 };
 
 hipError_t launch_apply_f64(const DevPlan &p, const double *u, double *y, bool accumulate, hipStream_t s);

@@ -206,173 +206,222 @@ __global__ __launch_bounds__(kBlockThreads) void face_kernel(
 }
 
 
-// Owner-computes apply.  Workgroup = one box of lattice nodes; it runs the same per-face pipeline
-// as face_kernel over every face whose patch meets the box (faces crossing the box boundary are
-// recomputed by each box they touch), keeps only the contributions to nodes inside the box,
-// sums them in an LDS accumulator, and finally writes each owned support node once with plain,
-// coalesced stores.  No global atomics, and y needs no prior zeroing.
-// VJP: x = w drives du; u2 = u gives the order-wise reduction, counted once per face (on the
-// face's primary visit).
+
+constexpr int kVisitChunk = 256;
+constexpr int kBoxThreads = 512;  // box kernel block size: 2 x the faces of a 256-thread batch in flight
+
+
+// Per-thread view of one face visit in a box: lattice address of the thread's normal line, its
+// accumulator address, the normal strides, and the expanded plane range.
+struct VisitPrep {
+  int64_t base;
+  int sn, abase, an, ilo, ihi;
+  bool live, prim;
+};
+
+template <int D, int K>
+__device__ __forceinline__ VisitPrep prep_visit(Visit vis, bool live, int t1, int t2, int s0, int s1, int s2,
+                                                int o0, int o1, int o2) {
+  constexpr int k = K - 1;
+  constexpr int NB = box_nodes(D, k), P = box_pitch(D, k), SY = P, SZ = P * NB;
+  VisitPrep q;
+  q.live = live;
+  const int c0 = (int)(vis & 0xFFFFF), c1 = (int)((vis >> 20) & 0xFFFFF), c2 = (int)((vis >> 40) & 0xFFFFF);
+  const int axis = (int)((vis >> 60) & 3);
+  const int half = (int)((vis >> 62) & 3);
+  q.prim = half != 2;
+  const bool ax0 = axis == 0, ax1 = axis == 1, ax2 = axis == 2;
+  // lattice strides along the normal and the tangential axes (ta < tb)
+  q.sn = ax0 ? s0 : (ax1 ? s1 : s2);
+  const int st1 = ax0 ? s1 : s0;
+  const int st2 = (D == 3) ? (ax2 ? s1 : s2) : 0;
+  q.base = (int64_t)k * ((int64_t)c0 * s0 + (int64_t)c1 * s1 + (int64_t)c2 * s2) + (int64_t)(t1 * st1 + t2 * st2);
+  // the same in the accumulator box
+  q.an = ax0 ? 1 : (ax1 ? SY : SZ);
+  const int a1 = ax0 ? SY : 1;
+  const int a2 = (D == 3) ? (ax2 ? SY : SZ) : 0;
+  q.abase = (k * c0 - o0) + SY * (k * c1 - o1) + (D == 3 ? SZ * (k * c2 - o2) : 0) + t1 * a1 + t2 * a2;
+  q.ilo = half == 2 ? k + 1 : 0;
+  q.ihi = half == 1 ? k : 2 * k;
+  return q;
+}
+
+// Box apply (default scatter).  Workgroup = one brick of cells; it runs the per-face pipeline of
+// face_kernel over every face with a cell in the brick, expanding only into the brick's cells (a face
+// split between two bricks is visited twice, once per half), and sums the results in a dense LDS
+// accumulator over the brick's node box.  Nodes that no other box contains are then written to y
+// with plain stores; nodes on shared box faces go to halo slots that halo_kernel adds into y.
+// No global atomics, and y needs no prior zeroing.
+// VJP: x = w drives du; u2 = u gives the order-wise reduction, counted on each face's primary visit.
 template <typename T, int D, int K, bool VJP>
-__global__ __launch_bounds__(kBlockThreads) void owner_kernel(
-    const T *__restrict__ x, const T *__restrict__ u2, T *__restrict__ y, double *__restrict__ partial,
-    const Leaf *__restrict__ leaves, const Visit *__restrict__ visits, const FlushRec *__restrict__ flushes,
-    const LineRec *__restrict__ lines, int acc_bytes, const T *__restrict__ tab, int s0, int s1, int s2,
-    int accumulate) {
+__global__ __launch_bounds__(kBoxThreads) void box_kernel(
+    const T *__restrict__ x, const T *__restrict__ u2, T *__restrict__ y, T *__restrict__ halo,
+    double *__restrict__ partial, const Box *__restrict__ boxes, const Visit *__restrict__ visits,
+    const BoxLine *__restrict__ lines, const T *__restrict__ tab, int s0, int s1, int s2, int accumulate) {
   constexpr int k = K - 1, NN = 2 * k + 1;
-  constexpr int TL = lines_per_face(D, k), FPB = faces_per_block(D, k), NT = TL * FPB;
-  __shared__ T sa[FPB * k * TL];
-  __shared__ T sb[FPB * k * TL];
-  extern __shared__ __align__(16) unsigned char dyn_smem[];
-  T *acc = reinterpret_cast<T *>(dyn_smem);
-  int *table = reinterpret_cast<int *>(dyn_smem + acc_bytes);
+  constexpr int TL = lines_per_face(D, k), FPB = kBoxThreads / TL, NT = TL * FPB;
+  constexpr int NB = box_nodes(D, k), P = box_pitch(D, k), ACC = box_acc(D, k);
+  constexpr int SY = P, SZ = P * NB;  // accumulator strides
+  __shared__ T acc[ACC];
+  __shared__ T sa[FPB * k * TL];  // per-face k x (k+1)^(d-1) values, transformed in place
   const T *g = tab;
   const T *gs = tab + k * NN;
   const T *M = tab + 2 * k * NN;
 
-  const int li = xcd_remap(blockIdx.x, gridDim.x);
-  const Leaf lf = leaves[li];
+  const int bi = xcd_remap(blockIdx.x, gridDim.x);
+  // box fields as wave-uniform scalars (kept in SGPRs)
+  const Box *bp = boxes + bi;
+  const int o0 = __builtin_amdgcn_readfirstlane(bp->org[0]);
+  const int o1 = __builtin_amdgcn_readfirstlane(bp->org[1]);
+  const int o2 = __builtin_amdgcn_readfirstlane(bp->org[2]);
+  const int visit_first = __builtin_amdgcn_readfirstlane(bp->visit_first);
+  const int visit_count = __builtin_amdgcn_readfirstlane(bp->visit_count);
+  const int line_first = __builtin_amdgcn_readfirstlane(bp->line_first);
+  const int line_count = __builtin_amdgcn_readfirstlane(bp->line_count);
   const int tid = threadIdx.x;
-  for (int i = tid; i < lf.acc_size; i += kBlockThreads) acc[i] = T(0);
-  for (int i = tid; i < lf.line_count; i += kBlockThreads) {
-    const LineRec r = lines[lf.line_first + i];
-    table[r.line] = r.base;
+  for (int i = tid; i < ACC; i += kBoxThreads) acc[i] = T(0);
+  // Flush plan: a group of G lanes takes one touched x-line of the box, lane = box x coordinate, so
+  // the stores of a group are consecutive.  Accumulating applies need y at the exclusive nodes: load
+  // it now, the face work hides the latency.
+  constexpr int G = (D == 3) ? 16 : 64, kGroups = kBoxThreads / G, kPre = (D == 3) ? 8 : 4;
+  const int grp = tid / G, gx = tid % G;
+  const int64_t box_base = (int64_t)o0 + (int64_t)s1 * o1 + (int64_t)s2 * o2;
+  T ypre[kPre];
+#pragma unroll
+  for (int m = 0; m < kPre; ++m) {
+    ypre[m] = T(0);
+    const int r = grp + m * kGroups;
+    if (accumulate && r < line_count) {
+      const BoxLine bl = lines[line_first + r];
+      const uint64_t bit = (uint64_t)1 << gx;
+      if ((bl.touched & bit) && !(bl.shared & bit)) {
+        const int ry = bl.line % NB, rz = bl.line / NB;
+        ypre[m] = y[box_base + gx + (int64_t)s1 * ry + (int64_t)s2 * rz];
+      }
+    }
   }
   const int f = tid / TL, t = tid - f * TL;
   const bool in_block = tid < NT;
   const int t1 = (D == 3) ? t % K : t;
   const int t2 = (D == 3) ? t / K : 0;
-  const int w1 = lf.hi[1] - lf.lo[1];
   double pj[k];
 #pragma unroll
   for (int j = 0; j < k; ++j) pj[j] = 0.0;
   __syncthreads();
 
-  for (int v0 = 0; v0 < lf.visit_count; v0 += FPB) {
-    const int vi = v0 + f;
-    const bool live = in_block && vi < lf.visit_count;
-    const Visit vis = live ? visits[lf.visit_first + vi] : Visit(0);
-    const int c0 = (int)(vis & 0xFFFFF), c1 = (int)((vis >> 20) & 0xFFFFF), c2 = (int)((vis >> 40) & 0xFFFFF);
-    const int axis = (int)((vis >> 60) & 3);
-    const bool prim = ((vis >> 62) & 1) != 0;
-    // normal axis n and tangential axes ta < tb, resolved with selects (no indexed local arrays)
-    const bool ax0 = axis == 0, ax1 = axis == 1, ax2 = axis == 2;
-    const int sn = ax0 ? s0 : (ax1 ? s1 : s2);
-    const int st1 = ax0 ? s1 : s0;
-    const int st2 = (D == 3) ? (ax2 ? s1 : s2) : 0;
-    const int64_t base = (int64_t)k * ((int64_t)c0 * s0 + (int64_t)c1 * s1 + (int64_t)c2 * s2) +
-                         (int64_t)(t1 * st1 + t2 * st2);
+  // The brick's visits are staged in LDS, and the gather of batch b+1 is issued before the work on
+  // batch b, so global-memory latency overlaps the contractions, barriers and LDS accumulation.
+  __shared__ Visit svis[kVisitChunk];
+  for (int vc = 0; vc < visit_count; vc += kVisitChunk) {
+    const int nv = min(visit_count - vc, kVisitChunk);
+    __syncthreads();
+    for (int i = tid; i < nv; i += kBoxThreads) svis[i] = visits[visit_first + vc + i];
+    __syncthreads();
+    VisitPrep nxt = prep_visit<D, K>(in_block && f < nv ? svis[f] : Visit(0), in_block && f < nv, t1, t2, s0, s1,
+                                     s2, o0, o1, o2);
+    T lnext[NN], unext[NN];
+#pragma unroll
+    for (int i = 0; i < NN; ++i) {
+      lnext[i] = nxt.live ? x[nxt.base + i * nxt.sn] : T(0);
+      unext[i] = (VJP && nxt.live && nxt.prim) ? u2[nxt.base + i * nxt.sn] : T(0);
+    }
+  for (int v0 = 0; v0 < nv; v0 += FPB) {
+    const VisitPrep cur = nxt;
+    const bool live = cur.live, prim = cur.prim;
+    const int an = cur.an, abase = cur.abase, ilo = cur.ilo, ihi = cur.ihi;
+    T line[NN], uline[NN];
+#pragma unroll
+    for (int i = 0; i < NN; ++i) {
+      line[i] = lnext[i];
+      uline[i] = unext[i];
+    }
+    if (v0 + FPB < nv) {  // issue the next batch's gather
+      const int vi = v0 + FPB + f;
+      nxt = prep_visit<D, K>(in_block && vi < nv ? svis[vi] : Visit(0), in_block && vi < nv, t1, t2, s0, s1, s2, o0,
+                             o1, o2);
+#pragma unroll
+      for (int i = 0; i < NN; ++i) {
+        lnext[i] = nxt.live ? x[nxt.base + i * nxt.sn] : T(0);
+        unext[i] = (VJP && nxt.live && nxt.prim) ? u2[nxt.base + i * nxt.sn] : T(0);
+      }
+    }
 
     T a[k], au[k];
 #pragma unroll
-    for (int j = 0; j < k; ++j) a[j] = au[j] = T(0);
-    if (live) {
-      T line[NN];
+    for (int j = 0; j < k; ++j) {
+      T s = T(0), su = T(0);
 #pragma unroll
-      for (int i = 0; i < NN; ++i) line[i] = x[base + i * sn];
-#pragma unroll
-      for (int j = 0; j < k; ++j) {
-        T s = T(0);
-#pragma unroll
-        for (int i = 0; i < NN; ++i) s = fma(g[j * NN + i], line[i], s);
-        a[j] = s;
+      for (int i = 0; i < NN; ++i) {
+        s = fma(g[j * NN + i], line[i], s);
+        if (VJP) su = fma(g[j * NN + i], uline[i], su);
       }
-      if (VJP && prim) {
-#pragma unroll
-        for (int i = 0; i < NN; ++i) line[i] = u2[base + i * sn];
-#pragma unroll
-        for (int j = 0; j < k; ++j) {
-          T s = T(0);
-#pragma unroll
-          for (int i = 0; i < NN; ++i) s = fma(g[j * NN + i], line[i], s);
-          au[j] = s;
-        }
-      }
+      a[j] = live ? s : T(0);
+      au[j] = (VJP && live && prim) ? su : T(0);
     }
     if (in_block) {
 #pragma unroll
       for (int j = 0; j < k; ++j) sa[(f * k + j) * TL + t] = a[j];
     }
     __syncthreads();
-    const T *res;
+    // tangential masses in place: each row (column) is read and rewritten by the one thread that owns
+    // it, and the barrier between the passes orders the row writes before the column reads
     if (D == 3) {
       if (in_block && t1 < k) {
-        const T *row = &sa[(f * k + t1) * TL + t2 * K];
+        T *row = &sa[(f * k + t1) * TL + t2 * K];
         T r[K];
 #pragma unroll
         for (int m = 0; m < K; ++m) r[m] = row[m];
-        T *out = &sb[(f * k + t1) * TL + t2 * K];
 #pragma unroll
         for (int q = 0; q < K; ++q) {
           T s = T(0);
 #pragma unroll
           for (int m = 0; m < K; ++m) s = fma(M[q * K + m], r[m], s);
-          out[q] = s;
+          row[q] = s;
         }
       }
       __syncthreads();
       if (in_block && t2 < k) {
-        const T *col = &sb[(f * k + t2) * TL + t1];
+        T *col = &sa[(f * k + t2) * TL + t1];
         T r[K];
 #pragma unroll
         for (int m = 0; m < K; ++m) r[m] = col[m * K];
-        T *out = &sa[(f * k + t2) * TL + t1];
 #pragma unroll
         for (int q = 0; q < K; ++q) {
           T s = T(0);
 #pragma unroll
           for (int m = 0; m < K; ++m) s = fma(M[q * K + m], r[m], s);
-          out[q * K] = s;
+          col[q * K] = s;
         }
       }
       __syncthreads();
-      res = sa;
     } else {
       if (in_block && t < k) {
-        const T *row = &sa[(f * k + t) * TL];
+        T *row = &sa[(f * k + t) * TL];
         T r[K];
 #pragma unroll
         for (int m = 0; m < K; ++m) r[m] = row[m];
-        T *out = &sb[(f * k + t) * TL];
 #pragma unroll
         for (int q = 0; q < K; ++q) {
           T s = T(0);
 #pragma unroll
           for (int m = 0; m < K; ++m) s = fma(M[q * K + m], r[m], s);
-          out[q] = s;
+          row[q] = s;
         }
       }
       __syncthreads();
-      res = sb;
     }
+    const T *res = sa;
     T cj[k];
 #pragma unroll
     for (int j = 0; j < k; ++j) cj[j] = in_block ? res[(f * k + j) * TL + t] : T(0);
     if (live) {
-      // node coordinates: along the normal n0 + i, along the tangential axes ia, ib (fixed per thread)
-      const int n0 = k * (ax0 ? c0 : (ax1 ? c1 : c2));
-      const int ia = k * (ax0 ? c1 : c0) + t1;
-      const int ib = (D == 3) ? k * (ax2 ? c1 : c2) + t2 : 0;
-      const int lo_n = ax0 ? lf.lo[0] : (ax1 ? lf.lo[1] : lf.lo[2]);
-      const int hi_n = ax0 ? lf.hi[0] : (ax1 ? lf.hi[1] : lf.hi[2]);
-      const int lo_a = ax0 ? lf.lo[1] : lf.lo[0], hi_a = ax0 ? lf.hi[1] : lf.hi[0];
-      const int lo_b = ax2 ? lf.lo[1] : lf.lo[2], hi_b = ax2 ? lf.hi[1] : lf.hi[2];
-      bool own_t = ia >= lo_a && ia < hi_a;
-      if (D == 3) own_t = own_t && ib >= lo_b && ib < hi_b;
-      if (own_t) {
 #pragma unroll
-        for (int i = 0; i < NN; ++i) {
-          const int in = n0 + i;
-          if (in >= lo_n && in < hi_n) {
-            T s = T(0);
+      for (int i = 0; i < NN; ++i) {
+        if (i >= ilo && i <= ihi) {
+          T s = T(0);
 #pragma unroll
-            for (int j = 0; j < k; ++j) s = fma(gs[j * NN + i], cj[j], s);
-            const int x0 = ax0 ? in : ia;
-            const int x1 = ax1 ? in : (ax0 ? ia : ib);
-            const int x2 = (D == 3) ? (ax2 ? in : ib) : 0;
-            const int ln = (x1 - lf.lo[1]) + w1 * (x2 - lf.lo[2]);
-            __hip_atomic_fetch_add(&acc[table[ln] + x0], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          }
+          for (int j = 0; j < k; ++j) s = fma(gs[j * NN + i], cj[j], s);
+          __hip_atomic_fetch_add(&acc[abase + i * an], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
       if (VJP && prim) {
@@ -380,22 +429,31 @@ __global__ __launch_bounds__(kBlockThreads) void owner_kernel(
         for (int j = 0; j < k; ++j) pj[j] += (double)au[j] * (double)cj[j];
       }
     }
-    __syncthreads();  // sa / sb are reused by the next batch
+    __syncthreads();  // sa / sb are reused by the next batch, acc is complete after the last
+  }
   }
 
-  // flush: 8 lanes per run of owned support nodes
-  const int sub = tid >> 3, sl = tid & 7;
-  for (int r = sub; r < lf.flush_count; r += kBlockThreads / 8) {
-    const FlushRec fr = flushes[lf.flush_first + r];
-    for (int i = sl; i < fr.len; i += 8) {
-      const T v = acc[fr.acc + i];
-      T *p = y + fr.start + i;
-      *p = accumulate ? *p + v : v;
+  // flush
+  for (int r = grp, m = 0; r < line_count; r += kGroups, ++m) {
+    const BoxLine bl = lines[line_first + r];
+    const uint64_t bit = (uint64_t)1 << gx;
+    if (!(bl.touched & bit)) continue;
+    const int ry = bl.line % NB, rz = bl.line / NB;
+    const T v = acc[gx + SY * ry + SZ * rz];
+    if (bl.shared & bit) {
+      halo[bl.slot_base + __popcll(bl.shared & (bit - 1))] = v;
+    } else {
+      T *p = y + box_base + gx + (int64_t)s1 * ry + (int64_t)s2 * rz;
+      T pv = T(0);
+#pragma unroll
+      for (int mm = 0; mm < kPre; ++mm)
+        if (mm == m) pv = ypre[mm];
+      *p = m < kPre ? pv + v : (accumulate ? *p + v : v);
     }
   }
 
   if (VJP) {
-    __shared__ double red[kBlockThreads / 64][k];
+    __shared__ double red[kBoxThreads / 64][k];
     const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int j = 0; j < k; ++j) {
@@ -408,10 +466,22 @@ __global__ __launch_bounds__(kBlockThreads) void owner_kernel(
     if (tid < k) {
       double s = 0.0;
 #pragma unroll
-      for (int w = 0; w < kBlockThreads / 64; ++w) s += red[w][tid];
-      partial[(int64_t)li * k + tid] = s;
+      for (int w = 0; w < kBoxThreads / 64; ++w) s += red[w][tid];
+      partial[(int64_t)bi * k + tid] = s;
     }
   }
+}
+
+// y[node] (+)= sum of the node's halo slots, for every support node on a shared box face.
+template <typename T>
+__global__ void halo_kernel(T *__restrict__ y, const T *__restrict__ halo, const int64_t *__restrict__ node,
+                            const int32_t *__restrict__ ptr, const int32_t *__restrict__ slot, int n, int accumulate) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= n) return;
+  T s = T(0);
+  for (int q = ptr[h]; q < ptr[h + 1]; ++q) s += halo[slot[q]];
+  T *p = y + node[h];
+  *p = accumulate ? *p + s : s;
 }
 
 template <typename T>
@@ -520,24 +590,26 @@ hipError_t dispatch(const DevPlan &p, const T *x, const T *u2, T *y, double *par
 
 
 template <typename T, bool VJP>
-hipError_t dispatch_owner(const DevPlan &p, const T *x, const T *u2, T *y, const T *tab, bool accumulate,
-                          hipStream_t s) {
-  if (p.n_leaves <= 0) return hipSuccess;
-  const int acc_bytes = ((p.max_acc * (int)sizeof(T)) + 15) / 16 * 16;
-  const size_t shmem = (size_t)acc_bytes + (size_t)p.max_lines * sizeof(int);
-  const dim3 grid(p.n_leaves), block(kBlockThreads);
-#define GHOST_OCASE(D_, K_)                                                                                     \
-  if (p.dim == D_ && p.k + 1 == K_) {                                                                          \
-    hipLaunchKernelGGL((owner_kernel<T, D_, K_, VJP>), grid, block, shmem, s, x, u2, y, p.vjp_partial, p.leaves, \
-                       p.visits, p.flushes, p.lines, acc_bytes, tab, p.stride[0], p.stride[1], p.stride[2],   \
-                       (int)accumulate);                                                                        \
-    return hipGetLastError();                                                                                   \
+hipError_t dispatch_box(const DevPlan &p, const T *x, const T *u2, T *y, const T *tab, bool accumulate,
+                        hipStream_t s) {
+  if (p.n_boxes <= 0) return hipSuccess;
+  T *halo = reinterpret_cast<T *>(p.halo);
+  const dim3 grid(p.n_boxes), block(kBoxThreads);
+  hipError_t e = hipErrorInvalidValue;
+#define GHOST_BCASE(D_, K_)                                                                                    \
+  if (p.dim == D_ && p.k + 1 == K_) {                                                                         \
+    hipLaunchKernelGGL((box_kernel<T, D_, K_, VJP>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes, \
+                       p.visits, p.box_lines, tab, p.stride[0], p.stride[1], p.stride[2], (int)accumulate);    \
+    e = hipGetLastError();                                                                                     \
   }
-  GHOST_OCASE(2, 2) GHOST_OCASE(2, 3) GHOST_OCASE(2, 4) GHOST_OCASE(2, 5) GHOST_OCASE(2, 6) GHOST_OCASE(2, 7)
-  GHOST_OCASE(2, 8) GHOST_OCASE(3, 2) GHOST_OCASE(3, 3) GHOST_OCASE(3, 4) GHOST_OCASE(3, 5) GHOST_OCASE(3, 6)
-  GHOST_OCASE(3, 7) GHOST_OCASE(3, 8)
-#undef GHOST_OCASE
-  return hipErrorInvalidValue;
+  GHOST_BCASE(2, 2) GHOST_BCASE(2, 3) GHOST_BCASE(2, 4) GHOST_BCASE(2, 5) GHOST_BCASE(2, 6) GHOST_BCASE(2, 7)
+  GHOST_BCASE(2, 8) GHOST_BCASE(3, 2) GHOST_BCASE(3, 3) GHOST_BCASE(3, 4) GHOST_BCASE(3, 5) GHOST_BCASE(3, 6)
+  GHOST_BCASE(3, 7) GHOST_BCASE(3, 8)
+#undef GHOST_BCASE
+  if (e != hipSuccess || p.n_halo == 0) return e;
+  hipLaunchKernelGGL((halo_kernel<T>), dim3((p.n_halo + kBlockThreads - 1) / kBlockThreads), dim3(kBlockThreads), 0,
+                     s, y, (const T *)halo, p.halo_node, p.halo_ptr, p.halo_slot, p.n_halo, (int)accumulate);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -564,7 +636,7 @@ hipError_t run_faces(const DevPlan &p, const T *x, const T *u2, T *y, const T *t
 }  // namespace
 
 hipError_t launch_apply_f64(const DevPlan &p, const double *u, double *y, bool accumulate, hipStream_t s) {
-  if (p.scatter == Scatter::Owner) return dispatch_owner<double, false>(p, u, nullptr, y, p.tab64, accumulate, s);
+  if (p.scatter == Scatter::Owner) return dispatch_box<double, false>(p, u, nullptr, y, p.tab64, accumulate, s);
   if (!accumulate) {
     hipError_t e = zero_support(p, y, s);
     if (e != hipSuccess) return e;
@@ -573,7 +645,7 @@ hipError_t launch_apply_f64(const DevPlan &p, const double *u, double *y, bool a
 }
 
 hipError_t launch_apply_f32(const DevPlan &p, const float *u, float *y, bool accumulate, hipStream_t s) {
-  if (p.scatter == Scatter::Owner) return dispatch_owner<float, false>(p, u, nullptr, y, p.tab32, accumulate, s);
+  if (p.scatter == Scatter::Owner) return dispatch_box<float, false>(p, u, nullptr, y, p.tab32, accumulate, s);
   if (!accumulate) {
     hipError_t e = zero_support(p, y, s);
     if (e != hipSuccess) return e;
@@ -584,10 +656,10 @@ hipError_t launch_apply_f32(const DevPlan &p, const float *u, float *y, bool acc
 hipError_t launch_vjp(const DevPlan &p, const double *u, const double *w, double *du, double *dgamma,
                       bool accumulate, hipStream_t s) {
   const bool owner = p.scatter == Scatter::Owner;
-  const int n_parts = owner ? p.n_leaves : p.n_batches;
+  const int n_parts = owner ? p.n_boxes : p.n_batches;
   hipError_t e = hipSuccess;
   if (owner) {
-    e = dispatch_owner<double, true>(p, w, u, du, p.tab64, accumulate, s);
+    e = dispatch_box<double, true>(p, w, u, du, p.tab64, accumulate, s);
   } else {
     if (!accumulate) e = zero_support(p, du, s);
     if (e == hipSuccess) e = run_faces<double, true>(p, w, u, du, p.tab64, s);

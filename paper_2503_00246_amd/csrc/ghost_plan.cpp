@@ -426,13 +426,9 @@ std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], dou
     merge_runs(iv, p.L[0], p.active_runs, p.n_active);
   }
 
-  // ---- owner-computes layout
+  // ---- box layout for the default scatter
   {
-    int brick = default_brick(dim, k);
-    int cap = kDefaultAccCap;
-    if (const char *e = std::getenv("GHOST_BRICK")) brick = std::max(1, std::atoi(e));
-    if (const char *e = std::getenv("GHOST_ACC_CAP")) cap = std::max(64, std::atoi(e));
-    std::string err = build_owner_layout(p, brick, cap);
+    std::string err = build_box_layout(p);
     if (!err.empty()) return err;
   }
 
@@ -446,189 +442,161 @@ std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], dou
   return "";
 }
 
-int default_brick(int dim, int k) {
-  if (dim == 2) return 32;
-  // measured on MI355X (128^3 Q5, 64^3 Q3, 96^3 Q7 balls): smaller boxes give more parallelism at
-  // the price of more recomputed faces; these are the fastest sizes found
-  static const int table[8] = {0, 8, 6, 3, 3, 4, 3, 2};
-  return table[std::min(std::max(k, 1), 7)];
-}
-
-std::string build_owner_layout(Plan &p, int B, int cap) {
+std::string build_box_layout(Plan &p) {
   const int d = p.dim, k = p.k;
+  const int B = box_cells(d, k), NB = box_nodes(d, k), P = box_pitch(d, k);
   const int64_t kB = (int64_t)k * B;
-  int NB[3] = {1, 1, 1};
-  for (int a = 0; a < d; ++a) NB[a] = (p.n[a] + B - 1) / B;
-  auto bidx = [&](int a, int64_t I) { return (int)std::min<int64_t>(I / kB, NB[a] - 1); };
-  auto blo = [&](int a, int b) { return a < d ? (int64_t)kB * b : (int64_t)0; };
-  auto bhi = [&](int a, int b) { return a < d ? (b == NB[a] - 1 ? p.L[a] : kB * (b + 1)) : (int64_t)1; };
-  const int64_t nbricks = (int64_t)NB[0] * NB[1] * NB[2];
+  int nbr[3] = {1, 1, 1};
+  for (int a = 0; a < d; ++a) nbr[a] = (p.n[a] + B - 1) / B;
+  const int64_t nbricks = (int64_t)nbr[0] * nbr[1] * nbr[2];
+  auto bid = [&](const int b[3]) { return b[0] + (int64_t)nbr[0] * (b[1] + (int64_t)nbr[1] * b[2]); };
 
-  struct Seg { int32_t I1, I2, x0, x1; };
-  std::vector<std::vector<Seg>> bseg(nbricks);
-  for (const Run &r : p.support_runs) {
-    const int64_t line = r.start / p.L[0];
-    const int64_t x0 = r.start % p.L[0], x1 = x0 + r.len;
-    const int32_t I1 = (int32_t)(line % p.L[1]), I2 = (int32_t)(line / p.L[1]);
-    const int b1 = d >= 2 ? bidx(1, I1) : 0, b2 = d >= 3 ? bidx(2, I2) : 0;
-    int64_t x = x0;
-    while (x < x1) {
-      const int bx = bidx(0, x);
-      const int64_t xe = std::min<int64_t>(x1, bhi(0, bx));
-      bseg[bx + (int64_t)NB[0] * (b1 + (int64_t)NB[1] * b2)].push_back({I1, I2, (int32_t)x, (int32_t)xe});
-      x = xe;
-    }
-  }
-
-  struct Box { int64_t lo[3], hi[3]; std::vector<Seg> segs; int64_t brick; };
-  auto need = [](const std::vector<Seg> &segs) {
-    std::vector<Seg> s = segs;
-    std::sort(s.begin(), s.end(), [](const Seg &x, const Seg &y) {
-      return x.I2 != y.I2 ? x.I2 < y.I2 : (x.I1 != y.I1 ? x.I1 < y.I1 : x.x0 < y.x0);
-    });
-    int64_t tot = 0;
-    size_t i = 0;
-    while (i < s.size()) {
-      int32_t lo = s[i].x0, hi = s[i].x1;
-      size_t j = i + 1;
-      while (j < s.size() && s[j].I1 == s[i].I1 && s[j].I2 == s[i].I2) hi = std::max(hi, s[j++].x1);
-      tot += hi - lo;
-      i = j;
-    }
-    return tot;
-  };
-  std::vector<Box> leaves;
-  std::vector<std::vector<int>> brick_leaves(nbricks);
-  std::vector<Box> stack;
-  for (int64_t b = 0; b < nbricks; ++b) {
-    if (bseg[b].empty()) continue;
-    Box bx;
-    const int bb[3] = {(int)(b % NB[0]), (int)((b / NB[0]) % NB[1]), (int)(b / ((int64_t)NB[0] * NB[1]))};
-    for (int a = 0; a < 3; ++a) { bx.lo[a] = blo(a, bb[a]); bx.hi[a] = bhi(a, bb[a]); }
-    bx.segs.swap(bseg[b]);
-    bx.brick = b;
-    stack.push_back(std::move(bx));
-    while (!stack.empty()) {
-      Box cur = std::move(stack.back());
-      stack.pop_back();
-      int ax = -1;
-      int64_t best = 0;
-      for (int a = 0; a < d; ++a) {
-        const int64_t cells = (cur.hi[a] - cur.lo[a]) / k;
-        if (cells >= 2 && cells > best) { best = cells; ax = a; }
-      }
-      if (need(cur.segs) <= cap || ax < 0) {
-        if (need(cur.segs) > cap) return "owner layout: a single cell exceeds the accumulator capacity";
-        brick_leaves[b].push_back((int)leaves.size());
-        leaves.push_back(std::move(cur));
-        continue;
-      }
-      const int64_t mid = cur.lo[ax] + (int64_t)k * (best / 2);
-      Box lo_b, hi_b;
-      for (int a = 0; a < 3; ++a) { lo_b.lo[a] = hi_b.lo[a] = cur.lo[a]; lo_b.hi[a] = hi_b.hi[a] = cur.hi[a]; }
-      lo_b.hi[ax] = mid;
-      hi_b.lo[ax] = mid;
-      lo_b.brick = hi_b.brick = b;
-      for (const Seg &sg : cur.segs) {
-        if (ax == 0) {
-          if (sg.x0 < mid) lo_b.segs.push_back({sg.I1, sg.I2, sg.x0, (int32_t)std::min<int64_t>(sg.x1, mid)});
-          if (sg.x1 > mid) hi_b.segs.push_back({sg.I1, sg.I2, (int32_t)std::max<int64_t>(sg.x0, mid), sg.x1});
-        } else {
-          const int64_t I = ax == 1 ? sg.I1 : sg.I2;
-          (I < mid ? lo_b : hi_b).segs.push_back(sg);
-        }
-      }
-      if (!hi_b.segs.empty()) stack.push_back(std::move(hi_b));
-      if (!lo_b.segs.empty()) stack.push_back(std::move(lo_b));
-    }
-  }
-
-  // launch order: Morton order of the box corner (in cells)
-  std::vector<std::pair<uint64_t, int>> order;
-  for (size_t i = 0; i < leaves.size(); ++i) {
-    int32_t c[3] = {(int32_t)(leaves[i].lo[0] / k), (int32_t)(leaves[i].lo[1] / k), (int32_t)(leaves[i].lo[2] / k)};
-    order.push_back({morton(d, c), (int)i});
-  }
-  std::sort(order.begin(), order.end());
-  std::vector<int> rank(leaves.size());
-  for (size_t r = 0; r < order.size(); ++r) rank[order[r].second] = (int)r;
-
-  // visits: every face whose patch box meets a leaf box
-  std::vector<std::vector<Visit>> lv(leaves.size());
+  // visits per brick
+  std::vector<std::vector<Visit>> bv(nbricks);
   for (int a = 0; a < d; ++a) {
     const size_t nf = p.face_cell[a].size() / 3;
     for (size_t f = 0; f < nf; ++f) {
       const int32_t *c = &p.face_cell[a][3 * f];
-      int64_t plo[3], phi[3];
-      for (int t = 0; t < 3; ++t) {
-        plo[t] = t < d ? (int64_t)k * c[t] : 0;
-        phi[t] = t < d ? plo[t] + (t == a ? 2 * k + 1 : k + 1) : 1;
-      }
-      int b0[3], b1[3];
-      for (int t = 0; t < 3; ++t) {
-        b0[t] = t < d ? bidx(t, plo[t]) : 0;
-        b1[t] = t < d ? bidx(t, phi[t] - 1) : 0;
+      int bl[3] = {0, 0, 0}, bu[3] = {0, 0, 0};
+      for (int t = 0; t < d; ++t) {
+        bl[t] = c[t] / B;
+        bu[t] = (c[t] + (t == a ? 1 : 0)) / B;
       }
       const Visit base = (Visit)c[0] | (Visit)c[1] << 20 | (Visit)c[2] << 40 | (Visit)a << 60;
-      for (int z = b0[2]; z <= b1[2]; ++z)
-        for (int y = b0[1]; y <= b1[1]; ++y)
-          for (int x = b0[0]; x <= b1[0]; ++x)
-            for (int li : brick_leaves[x + (int64_t)NB[0] * (y + (int64_t)NB[1] * z)]) {
-              const Box &bx = leaves[li];
-              bool hit = true, prim = true;
-              for (int t = 0; t < 3; ++t) {
-                hit = hit && plo[t] < bx.hi[t] && phi[t] > bx.lo[t];
-                prim = prim && plo[t] >= bx.lo[t] && plo[t] < bx.hi[t];
-              }
-              if (hit) lv[li].push_back(base | (Visit)(prim ? 1 : 0) << 62);
-            }
+      if (bl[a] == bu[a]) {
+        bv[bid(bl)].push_back(base);
+      } else {
+        bv[bid(bl)].push_back(base | (Visit)1 << 62);
+        bv[bid(bu)].push_back(base | (Visit)2 << 62);
+      }
     }
   }
 
-  p.brick = B;
-  p.leaves.clear();
-  p.visits.clear();
-  p.flushes.clear();
-  p.lines.clear();
-  p.max_acc = 0;
-  p.max_lines_box = 0;
-  for (const auto &o : order) {
-    const Box &bx = leaves[o.second];
-    Leaf lf{};
-    for (int a = 0; a < 3; ++a) { lf.lo[a] = (int32_t)bx.lo[a]; lf.hi[a] = (int32_t)bx.hi[a]; }
-    lf.visit_first = (int32_t)p.visits.size();
-    lf.visit_count = (int32_t)lv[o.second].size();
-    p.visits.insert(p.visits.end(), lv[o.second].begin(), lv[o.second].end());
-    std::vector<Seg> s = bx.segs;
-    std::sort(s.begin(), s.end(), [](const Seg &x, const Seg &y) {
-      return x.I2 != y.I2 ? x.I2 < y.I2 : (x.I1 != y.I1 ? x.I1 < y.I1 : x.x0 < y.x0);
-    });
-    lf.flush_first = (int32_t)p.flushes.size();
-    lf.line_first = (int32_t)p.lines.size();
-    const int64_t w1 = bx.hi[1] - bx.lo[1];
-    int32_t acc = 0;
-    size_t i = 0;
-    while (i < s.size()) {
-      size_t j = i;
-      int32_t xlo = s[i].x0, xhi = s[i].x1;
-      while (j < s.size() && s[j].I1 == s[i].I1 && s[j].I2 == s[i].I2) xhi = std::max(xhi, s[j++].x1);
-      const int32_t line = (int32_t)((s[i].I1 - bx.lo[1]) + w1 * (s[i].I2 - bx.lo[2]));
-      p.lines.push_back({line, acc - xlo});
-      for (size_t q = i; q < j; ++q)
-        p.flushes.push_back({s[q].x0 + p.L[0] * (s[q].I1 + p.L[1] * (int64_t)s[q].I2), s[q].x1 - s[q].x0,
-                             acc + (s[q].x0 - xlo)});
-      acc += xhi - xlo;
-      i = j;
-    }
-    lf.flush_count = (int32_t)(p.flushes.size() - lf.flush_first);
-    lf.line_count = (int32_t)(p.lines.size() - lf.line_first);
-    lf.acc_size = acc;
-    p.max_acc = std::max(p.max_acc, acc);
-    p.max_lines_box = std::max<int>(p.max_lines_box, (int)(w1 * (bx.hi[2] - bx.lo[2])));
-    p.leaves.push_back(lf);
+  // launch order: Morton order of the brick
+  std::vector<std::pair<uint64_t, int64_t>> order;
+  for (int64_t b = 0; b < nbricks; ++b) {
+    if (bv[b].empty()) continue;
+    int32_t bc[3] = {(int32_t)(b % nbr[0]), (int32_t)((b / nbr[0]) % nbr[1]), (int32_t)(b / ((int64_t)nbr[0] * nbr[1]))};
+    order.push_back({morton(d, bc), b});
   }
+  std::sort(order.begin(), order.end());
+
+  p.brick = B;
+  p.box_nodes = NB;
+  p.boxes.clear();
+  p.visits.clear();
+  p.box_runs.clear();
+  p.box_lines.clear();
+  if (NB > 64) return "box node extent exceeds the 64-bit line masks";
+  struct HaloRef { int64_t node; int32_t slot; };
+  std::vector<HaloRef> halo;
+  int64_t slots = 0;
+  for (const auto &o : order) {
+    const int64_t b = o.second;
+    const int bb[3] = {(int)(b % nbr[0]), (int)((b / nbr[0]) % nbr[1]), (int)(b / ((int64_t)nbr[0] * nbr[1]))};
+    Box bx{};
+    bool sh_lo[3] = {false, false, false}, sh_hi[3] = {false, false, false};
+    for (int a = 0; a < 3; ++a) {
+      bx.org[a] = a < d ? (int32_t)(kB * bb[a]) : 0;
+      if (a < d) {
+        sh_lo[a] = bb[a] > 0;
+        sh_hi[a] = (int64_t)B * (bb[a] + 1) < p.n[a];
+      }
+    }
+    bx.visit_first = (int32_t)p.visits.size();
+    bx.visit_count = (int32_t)bv[b].size();
+    {
+      // Interleave the brick's visits so that the faces of one batch (consecutive visits) come from
+      // different parts of the brick and rarely add into the same accumulator nodes.
+      const size_t nv = bv[b].size(), fpb = (size_t)faces_per_block(d, k);
+      const size_t nbatch = (nv + fpb - 1) / fpb;
+      for (size_t q = 0; q < nbatch; ++q)
+        for (size_t r = 0; r < fpb; ++r)
+          if (q + r * nbatch < nv) p.visits.push_back(bv[b][q + r * nbatch]);
+    }
+
+    // nodes this brick contributes to: union over its visits of the expanded part of the patch
+    std::vector<Interval> iv;
+    for (Visit v : bv[b]) {
+      const int c[3] = {(int)(v & 0xFFFFF), (int)((v >> 20) & 0xFFFFF), (int)((v >> 40) & 0xFFFFF)};
+      const int a = (int)((v >> 60) & 3), half = (int)((v >> 62) & 3);
+      int64_t lo[3], hi[3];  // node ranges, inclusive
+      for (int t = 0; t < 3; ++t) {
+        lo[t] = t < d ? (int64_t)k * c[t] : 0;
+        hi[t] = t < d ? lo[t] + k : 0;
+      }
+      if (half == 0) hi[a] = lo[a] + 2 * k;
+      if (half == 2) { lo[a] = (int64_t)k * c[a] + k + 1; hi[a] = (int64_t)k * c[a] + 2 * k; }
+      for (int64_t z = lo[2]; z <= hi[2]; ++z)
+        for (int64_t y = lo[1]; y <= hi[1]; ++y) iv.push_back({y + p.L[1] * z, lo[0], hi[0] + 1});
+    }
+    std::vector<Run> runs;
+    int64_t tot = 0;
+    merge_runs(iv, p.L[0], runs, tot);
+    bx.run_first = (int32_t)p.box_runs.size();
+    bx.line_first = (int32_t)p.box_lines.size();
+    for (const Run &r : runs) {
+      const int64_t line = r.start / p.L[0], x0 = r.start % p.L[0];
+      const int64_t Y = line % p.L[1], Z = line / p.L[1];
+      const int64_t ry = d >= 2 ? Y - bx.org[1] : 0, rz = d >= 3 ? Z - bx.org[2] : 0;
+      const bool line_shared = (d >= 2 && ((ry == 0 && sh_lo[1]) || (ry == kB && sh_hi[1]))) ||
+                               (d >= 3 && ((rz == 0 && sh_lo[2]) || (rz == kB && sh_hi[2])));
+      // split the run at shared x-planes
+      int64_t x = x0;
+      const int64_t xe = x0 + r.len;
+      while (x < xe) {
+        const int64_t rx = x - bx.org[0];
+        const bool node_shared = line_shared || (rx == 0 && sh_lo[0]) || (rx == kB && sh_hi[0]);
+        int64_t e = x + 1;
+        if (!line_shared && !node_shared)
+          while (e < xe && !((e - bx.org[0] == kB) && sh_hi[0])) ++e;
+        else if (line_shared)
+          e = xe;
+        BoxRun br{};
+        br.start = x + p.L[0] * line;
+        br.acc = (int32_t)(rx + P * (ry + (int64_t)NB * rz));
+        br.len = (int32_t)(e - x);
+        br.slot = -1;
+        if (node_shared) {
+          br.slot = (int32_t)slots;
+          for (int64_t q = 0; q < br.len; ++q) halo.push_back({br.start + q, (int32_t)(slots + q)});
+          slots += br.len;
+        }
+        p.box_runs.push_back(br);
+        // device line record (runs of one line are consecutive: start a record at a new line)
+        const int32_t lrel = (int32_t)(ry + (int64_t)NB * rz);
+        if (p.box_lines.size() == (size_t)bx.line_first || p.box_lines.back().line != lrel)
+          p.box_lines.push_back(BoxLine{0, 0, lrel, (int32_t)(node_shared ? br.slot : slots)});
+        BoxLine &bl = p.box_lines.back();
+        for (int64_t q = 0; q < br.len; ++q) {
+          bl.touched |= (uint64_t)1 << (rx + q);
+          if (node_shared) bl.shared |= (uint64_t)1 << (rx + q);
+        }
+        x = e;
+      }
+    }
+    bx.run_count = (int32_t)(p.box_runs.size() - bx.run_first);
+    bx.line_count = (int32_t)(p.box_lines.size() - bx.line_first);
+    p.boxes.push_back(bx);
+  }
+  if (slots >= ((int64_t)1 << 31) || (int64_t)p.visits.size() >= ((int64_t)1 << 31))
+    return "box layout too large";
   p.n_visits = (int64_t)p.visits.size();
-  (void)rank;
+  p.n_slots = slots;
+  std::sort(halo.begin(), halo.end(), [](const HaloRef &x, const HaloRef &y) {
+    return x.node != y.node ? x.node < y.node : x.slot < y.slot;
+  });
+  p.halo_node.clear();
+  p.halo_ptr.clear();
+  p.halo_slot.clear();
+  for (size_t i = 0; i < halo.size(); ++i) {
+    if (i == 0 || halo[i].node != halo[i - 1].node) {
+      p.halo_node.push_back(halo[i].node);
+      p.halo_ptr.push_back((int32_t)p.halo_slot.size());
+    }
+    p.halo_slot.push_back(halo[i].slot);
+  }
+  p.halo_ptr.push_back((int32_t)p.halo_slot.size());
   return "";
 }
 

@@ -24,31 +24,39 @@ struct Run {            // maximal run of consecutive lattice nodes along x
   int32_t pad;
 };
 
-// Owner-computes scatter: a box of lattice nodes [lo, hi) owned by one workgroup, which applies every
-// face whose patch meets the box, accumulates the box's share in LDS and writes each owned support
-// node once.
-struct Leaf {
-  int32_t lo[3], hi[3];   // owned node ranges per axis
+// Box scatter: the cells are cut into bricks of B^d cells.  A workgroup handles one brick: it applies
+// every face with a cell in the brick (a face whose two cells lie in different bricks is visited by
+// both, each expanding only into its own cell; the shared node plane goes to the lower cell's brick),
+// sums the contributions over the brick's node box [org, org + kB] in a dense LDS accumulator, writes
+// nodes that no other box contains straight to y, and stores nodes on shared box faces into halo
+// slots, which a second kernel adds into y.
+struct Box {
+  int32_t org[3];         // node origin k*B*b (0 for unused axes)
   int32_t visit_first, visit_count;
-  int32_t flush_first, flush_count;
-  int32_t line_first, line_count;
-  int32_t acc_size;       // accumulator entries (sum of per-line spans)
-  int32_t pad;
+  int32_t run_first, run_count;   // inspection runs (BoxRun)
+  int32_t line_first, line_count; // device form: touched x-lines of the box (BoxLine)
 };
 
-// Packed face visit: lower cell c0 | c1 << 20 | c2 << 40 | axis << 60 | primary << 62.  The primary visit
-// of a face is the one by the box owning the face's first patch node (used to count it once).
+// One touched x-line of a box node box: bit x of `touched` marks box node x of the line as a node the
+// brick contributes to; bit x of `shared` marks it as lying on a box face shared with another brick
+// (its value goes to halo slot slot_base + (number of shared bits below x) instead of y).
+struct BoxLine {
+  uint64_t touched, shared;
+  int32_t line;        // ry + NB * rz (box-relative line coordinates)
+  int32_t slot_base;
+};
+
+// Packed face visit: c0 | c1 << 20 | c2 << 40 | axis << 60 | half << 62, half 0 = whole patch,
+// 1 = lower cell (patch planes 0..k), 2 = upper cell (planes k+1..2k).  A face's primary visit (the one
+// that counts it in reductions) is the one with half 0 or 1.
 using Visit = uint64_t;
 
-struct FlushRec {        // a run of owned support nodes along x and its place in the accumulator
+struct BoxRun {          // a run of touched box nodes along x
   int64_t start;         // lattice index of the first node
+  int32_t acc;           // accumulator index of the first node
   int32_t len;
-  int32_t acc;           // accumulator offset of the first node
-};
-
-struct LineRec {         // accumulator base of one owned x-line: acc offset of node x is base + x
-  int32_t line;          // (I1 - lo1) + (hi1 - lo1) * (I2 - lo2)
-  int32_t base;
+  int32_t slot;          // -1: exclusive, written to y; else first halo slot of the run
+  int32_t pad;
 };
 
 struct Plan {
@@ -74,14 +82,18 @@ struct Plan {
   std::vector<int64_t> face_base;      // lattice index of patch node (0,..,0), in batch order
   std::vector<int> colour_begin;       // coloured: batch range [colour_begin[c], colour_begin[c+1])
 
-  // owner-computes layout
-  int brick = 0;                       // cells per brick edge before splitting
-  std::vector<Leaf> leaves;            // launch order
+  // box layout
+  int brick = 0;                       // cells per brick edge
+  int box_nodes = 0;                   // k*brick + 1
+  std::vector<Box> boxes;              // launch order
   std::vector<Visit> visits;
-  std::vector<FlushRec> flushes;
-  std::vector<LineRec> lines;
+  std::vector<BoxRun> box_runs;       // inspection form of the flush
+  std::vector<BoxLine> box_lines;      // device form
   int64_t n_visits = 0;
-  int max_acc = 0, max_lines_box = 0;  // largest accumulator and line table over the leaves
+  int64_t n_slots = 0;                 // halo slots
+  std::vector<int64_t> halo_node;      // shared support nodes (lattice index), ascending
+  std::vector<int32_t> halo_ptr;       // slots of halo_node[h]: halo_slot[halo_ptr[h] .. halo_ptr[h+1])
+  std::vector<int32_t> halo_slot;
 
   std::vector<Run> support_runs;       // union of face patches
   int64_t n_support = 0;
@@ -100,12 +112,8 @@ std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], dou
                        int ls_kind, const double centre[3], double radius,
                        const signed char *cell_class, bool coloured);
 
-// Owner-computes layout for brick edge `brick` (cells) and accumulator capacity `acc_cap` (entries);
-// bricks whose accumulator would exceed the capacity are split.  Called by build_plan.
-std::string build_owner_layout(Plan &p, int brick, int acc_cap);
-
-// Default brick edge for a dimension and degree.
-int default_brick(int dim, int k);
+// Box layout (see Box).  Called by build_plan.
+std::string build_box_layout(Plan &p);
 
 // 1D tables in extended precision (exposed for the host tests through the ABI).
 void tables_1d(int k, std::vector<long double> &nodes, std::vector<long double> &weights,

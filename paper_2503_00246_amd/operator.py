@@ -181,20 +181,19 @@ class GhostOperator:
         L.check(self._lib.ghost_faces(self._h, axis, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nf))
         return out[:nf]
 
-    def owner_layout(self):
-        """Owner-computes layout: (boxes (nb, 10) int32, visits uint64, flush (nr, 3) int64)."""
+    def box_layout(self):
+        """Box-scatter layout: (boxes (nb, 7) int32, visits uint64, runs (nr, 4) int64)."""
         nb, nv = self.stats["n_boxes"], self.stats["n_visits"]
-        boxes = np.zeros((max(nb, 1), 10), dtype=np.int32)
+        boxes = np.zeros((max(nb, 1), 7), dtype=np.int32)
         visits = np.zeros(max(nv, 1), dtype=np.uint64)
-        L.check(self._lib.ghost_owner_layout(self._h, boxes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nb,
-                                             visits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nv, None, 0))
+        L.check(self._lib.ghost_box_layout(self._h, boxes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nb,
+                                           visits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nv, None, 0))
         boxes = boxes[:nb]
-        nr = int(boxes[:, 8].max() + boxes[:, 9][boxes[:, 8].argmax()]) if nb else 0
-        nr = int((boxes[:, 8] + boxes[:, 9]).max()) if nb else 0
-        flush = np.zeros((max(nr, 1), 3), dtype=np.int64)
-        L.check(self._lib.ghost_owner_layout(self._h, None, 0, None, 0,
-                                             flush.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nr))
-        return boxes, visits[:nv], flush[:nr]
+        nr = int((boxes[:, 5] + boxes[:, 6]).max()) if nb else 0
+        runs = np.zeros((max(nr, 1), 4), dtype=np.int64)
+        L.check(self._lib.ghost_box_layout(self._h, None, 0, None, 0,
+                                           runs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nr))
+        return boxes, visits[:nv], runs[:nr]
 
     def tables(self):
         k = self.k

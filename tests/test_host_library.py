@@ -184,63 +184,65 @@ def test_host_only_context_refuses_device_work(lib):
     lib.ghost_destroy(None)  # no-op
 
 
-@pytest.mark.parametrize("name,brick", [("disk2d_q2_32", None), ("ball3d_q3_64", None), ("ball3d_q3_64", "3"),
-                                        ("ball3d_q3_64", "5")])
-def test_owner_layout_partitions_support(name, brick, monkeypatch):
-    """Owner-computes layout: the flush runs partition the support exactly, every run lies in its
-    box, accumulator offsets of a box are disjoint, each box visits exactly the faces whose patch
-    meets it, and every face has exactly one primary visit (the box holding its first patch node)."""
-    cap = 6144
-    if brick:
-        cap = 700
-        monkeypatch.setenv("GHOST_BRICK", brick)
-        monkeypatch.setenv("GHOST_ACC_CAP", str(cap))  # force splitting
-    w = WORKLOADS[name]
+@pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64", "small3d_q5_24", "small3d_q7_14"])
+def test_box_layout(name):
+    """Box scatter layout: runs of all boxes cover the support exactly; a node is either exclusive to one
+    box (written to y) or routed through halo slots by every box touching it; each face is visited once
+    (whole patch) or twice (lower / upper cell, by the bricks of those cells); run accumulator indices
+    are the box-relative node coordinates."""
+    from paper_2503_00246_amd.workloads import Workload
+    extra = {"small3d_q5_24": Workload("s", 3, 5, (24,) * 3, (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73),
+             "small3d_q7_14": Workload("s", 3, 7, (14, 13, 12), (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)}
+    w = WORKLOADS.get(name) or extra[name]
     op = _host(w)
-    boxes, visits, flush = op.owner_layout()
-    assert op.stats["n_visits"] == len(visits) and 0 < op.stats["max_acc"] <= cap
-    L_ = np.array(list(w.lattice) + [1] * (3 - w.d))
+    boxes, visits, runs = op.box_layout()
+    d, k = w.d, w.k
+    B = 15 // k if d == 3 else 63 // k
+    NB = k * B + 1
+    P = NB if NB % 2 else NB + 1
+    assert op.stats["brick"] == B
+    L_ = np.array(list(w.lattice) + [1] * (3 - d))
     cls = omesh.classify_ball(w.n, w.lo, w.h, w.centre, w.radius)
     faces = omesh.ghost_faces(cls)
-    sup = np.unique(np.concatenate([omesh.patch_dofs(faces[a], w.k, a, w.lattice).ravel() for a in range(w.d)]))
-    covered = np.concatenate([np.arange(s_, s_ + n_) for s_, n_, _ in flush])
-    assert len(covered) == len(sup) and np.array_equal(np.sort(covered), sup)
-    lo, hi = boxes[:, 0:3].astype(np.int64), boxes[:, 3:6].astype(np.int64)
-    # runs inside their box, accumulator offsets disjoint per box
-    box_of_run = np.repeat(np.arange(len(boxes)), boxes[:, 9])
-    order = np.concatenate([np.arange(b[8], b[8] + b[9]) for b in boxes])
-    runs = flush[order]
-    I = np.stack([runs[:, 0] % L_[0], (runs[:, 0] // L_[0]) % L_[1], runs[:, 0] // (L_[0] * L_[1])], -1)
-    assert np.all(I >= lo[box_of_run]) and np.all(I < hi[box_of_run])
-    assert np.all(I[:, 0] + runs[:, 1] <= hi[box_of_run, 0])
-    for b in range(len(boxes)):
-        r = runs[box_of_run == b]
-        accs = np.concatenate([np.arange(a_, a_ + n_) for _, n_, a_ in r])
-        assert len(np.unique(accs)) == len(accs) and accs.min() >= 0
-    # visits: decode, compare with the boxes each face's patch meets
+    sup = np.unique(np.concatenate([omesh.patch_dofs(faces[a], k, a, w.lattice).ravel() for a in range(d)]))
+    # runs: cover the support; exclusive vs shared consistent
+    box_of_run = np.repeat(np.arange(len(boxes)), boxes[:, 6])
+    order = np.concatenate([np.arange(b[5], b[5] + b[6]) for b in boxes])
+    runs = runs[order]
+    nodes = np.concatenate([np.arange(s_, s_ + n_) for s_, _, n_, _ in runs])
+    shared = np.concatenate([np.full(n_, sl >= 0) for _, _, n_, sl in runs])
+    rbox = np.repeat(box_of_run, runs[:, 2])
+    assert np.array_equal(np.unique(nodes), sup)
+    excl_nodes = nodes[~shared]
+    assert len(np.unique(excl_nodes)) == len(excl_nodes)
+    assert len(np.intersect1d(excl_nodes, nodes[shared])) == 0
+    assert op.stats["n_halo_slots"] == int(shared.sum())
+    assert op.stats["n_halo_nodes"] == len(np.unique(nodes[shared]))
+    slots = np.concatenate([np.arange(sl, sl + n_) for _, _, n_, sl in runs if sl >= 0] + [np.zeros(0, np.int64)])
+    assert np.array_equal(np.sort(slots), np.arange(len(slots)))
+    # accumulator index = box-relative coordinates
+    I = np.stack([nodes % L_[0], (nodes // L_[0]) % L_[1], nodes // (L_[0] * L_[1])], -1)
+    rel = I - boxes[rbox, 0:3]
+    assert np.all(rel >= 0) and np.all(rel[:, :d] < NB)
+    accs = np.concatenate([np.arange(a_, a_ + n_) for _, a_, n_, _ in runs])
+    assert np.array_equal(accs, rel[:, 0] + P * (rel[:, 1] + NB * rel[:, 2]))
+    # visits
     v = visits.astype(np.uint64)
     c = np.stack([(v & 0xFFFFF), (v >> 20) & 0xFFFFF, (v >> 40) & 0xFFFFF], -1).astype(np.int64)
     ax = ((v >> 60) & 3).astype(np.int64)
-    prim = ((v >> 62) & 1).astype(bool)
-    box_of_visit = np.repeat(np.arange(len(boxes)), boxes[:, 7])
-    order = np.concatenate([np.arange(b[6], b[6] + b[7]) for b in boxes])
-    c, ax, prim = c[order], ax[order], prim[order]
-    key_dims = np.array([1, 1 << 21, 1 << 42])
-    got = np.unique(np.stack([box_of_visit, ax, c @ key_dims], -1), axis=0)
-    want = []
-    for a in range(w.d):
-        f = np.concatenate([faces[a], np.zeros((len(faces[a]), 3 - w.d), dtype=np.int64)], 1)
-        plo = w.k * f
-        ext = np.array([2 * w.k + 1 if t == a else (w.k + 1 if t < w.d else 1) for t in range(3)])
-        phi = plo + ext
-        hit = np.all((plo[:, None, :] < hi[None]) & (phi[:, None, :] > lo[None]), axis=-1)  # (nf, nb)
-        fi, bi = np.nonzero(hit)
-        want.append(np.stack([bi, np.full(len(bi), a), f[fi] @ key_dims], -1))
-    want = np.unique(np.concatenate(want), axis=0)
-    assert np.array_equal(got, want)
-    # one primary visit per face, in the box holding the patch's first node
-    pk = np.unique(np.stack([ax[prim], c[prim] @ key_dims], -1), axis=0)
-    assert len(pk) == prim.sum() == sum(len(faces[a]) for a in range(w.d))
-    first = w.k * c[prim]
-    bprim = box_of_visit[prim]
-    assert np.all(first >= lo[bprim]) and np.all(first < hi[bprim])
+    half = ((v >> 62) & 3).astype(np.int64)
+    vbox = np.repeat(np.arange(len(boxes)), boxes[:, 4])
+    vorder = np.concatenate([np.arange(b[3], b[3] + b[4]) for b in boxes])
+    c, ax, half = c[vorder], ax[vorder], half[vorder]
+    brick = boxes[vbox, 0:3] // (k * B)
+    lower = c // B
+    upper = (c + np.eye(3, dtype=np.int64)[ax]) // B
+    assert np.all(np.where((half == 2)[:, None], upper, lower)[:, :d] == brick[:, :d])
+    assert np.all(np.all(lower == upper, axis=1) == (half == 0))
+    key = ax * (1 << 60) + c[:, 0] + (c[:, 1] << 20) + (c[:, 2] << 40)
+    uk, cnt = np.unique(key, return_counts=True)
+    assert len(uk) == sum(len(faces[a]) for a in range(d))
+    halves = {}
+    for kk, h in zip(key, half):
+        halves.setdefault(int(kk), []).append(int(h))
+    assert all(sorted(h) in ([0], [1, 2]) for h in halves.values())
