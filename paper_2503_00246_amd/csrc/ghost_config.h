@@ -6,16 +6,21 @@ namespace ghost {
 constexpr int kMaxDegree = 7;
 constexpr int kBlockThreads = 256;
 
-// Box scatter: cells per brick edge, chosen so that a brick's node box (k*B + 1 nodes per axis) is
-// about 16 (3D) or 64 (2D) nodes, and the padded LDS accumulator of the box.
+// Box scatter: cells per brick edge, chosen so that a brick's node box (k*B + 1 nodes per axis) fits
+// the accumulator extent E (16 in 3D, 64 in 2D).  The accumulator is E^d values; node (x, y, z) of the
+// box lives at slot box_slot(x, y, z): each x-line is rotated by (5y + 11z) mod E, which spreads the
+// lanes of a face (consecutive y or z) over the LDS banks for every face orientation.
 #ifndef GHOST_BOX_SPAN
 #define GHOST_BOX_SPAN 15
 #endif
-constexpr int box_cells(int dim, int k) { return dim == 3 ? (GHOST_BOX_SPAN / k > 0 ? GHOST_BOX_SPAN / k : 1) : 63 / k; }
+constexpr int box_extent(int dim) { return dim == 3 ? 16 : 64; }
+constexpr int box_cells(int dim, int k) {
+  return dim == 3 ? (GHOST_BOX_SPAN / k > 0 ? GHOST_BOX_SPAN / k : 1) : (box_extent(2) - 1) / k;
+}
 constexpr int box_nodes(int dim, int k) { return k * box_cells(dim, k) + 1; }
-constexpr int box_pitch(int dim, int k) { return box_nodes(dim, k) | 1; }  // odd x-pitch: fewer bank conflicts
-constexpr int box_acc(int dim, int k) {
-  return dim == 3 ? box_pitch(dim, k) * box_nodes(dim, k) * box_nodes(dim, k) : box_pitch(dim, k) * box_nodes(dim, k);
+constexpr int box_acc(int dim) { return dim == 3 ? 16 * 16 * 16 : 64 * 64; }
+constexpr int box_slot(int dim, int x, int y, int z) {
+  return dim == 3 ? ((x + 5 * y + 11 * z) & 15) + 16 * y + 256 * z : ((x + 5 * y) & 63) + 64 * y;
 }
 
 // Threads per face: one per tangential node line, (k+1)^(d-1).

@@ -211,11 +211,13 @@ constexpr int kVisitChunk = 256;
 constexpr int kBoxThreads = 512;  // box kernel block size: 2 x the faces of a 256-thread batch in flight
 
 
-// Per-thread view of one face visit in a box: lattice address of the thread's normal line, its
-// accumulator address, the normal strides, and the expanded plane range.
+// Per-thread view of one face visit in a box: lattice address of the thread's normal line, the normal
+// stride, the line's box coordinates and the expanded plane range.
 struct VisitPrep {
-  int64_t base;
-  int sn, abase, an, ilo, ihi;
+  int64_t base;          // lattice index of the thread's normal line, patch plane 0
+  int sn;                // lattice stride along the normal
+  int axis, rn, ra, rb;  // normal axis; box coordinates: normal origin, tangential a / b of the line
+  int ilo, ihi;          // expanded patch planes
   bool live, prim;
 };
 
@@ -223,12 +225,12 @@ template <int D, int K>
 __device__ __forceinline__ VisitPrep prep_visit(Visit vis, bool live, int t1, int t2, int s0, int s1, int s2,
                                                 int o0, int o1, int o2) {
   constexpr int k = K - 1;
-  constexpr int NB = box_nodes(D, k), P = box_pitch(D, k), SY = P, SZ = P * NB;
   VisitPrep q;
   q.live = live;
   const int c0 = (int)(vis & 0xFFFFF), c1 = (int)((vis >> 20) & 0xFFFFF), c2 = (int)((vis >> 40) & 0xFFFFF);
   const int axis = (int)((vis >> 60) & 3);
   const int half = (int)((vis >> 62) & 3);
+  q.axis = axis;
   q.prim = half != 2;
   const bool ax0 = axis == 0, ax1 = axis == 1, ax2 = axis == 2;
   // lattice strides along the normal and the tangential axes (ta < tb)
@@ -236,11 +238,15 @@ __device__ __forceinline__ VisitPrep prep_visit(Visit vis, bool live, int t1, in
   const int st1 = ax0 ? s1 : s0;
   const int st2 = (D == 3) ? (ax2 ? s1 : s2) : 0;
   q.base = (int64_t)k * ((int64_t)c0 * s0 + (int64_t)c1 * s1 + (int64_t)c2 * s2) + (int64_t)(t1 * st1 + t2 * st2);
-  // the same in the accumulator box
-  q.an = ax0 ? 1 : (ax1 ? SY : SZ);
-  const int a1 = ax0 ? SY : 1;
-  const int a2 = (D == 3) ? (ax2 ? SY : SZ) : 0;
-  q.abase = (k * c0 - o0) + SY * (k * c1 - o1) + (D == 3 ? SZ * (k * c2 - o2) : 0) + t1 * a1 + t2 * a2;
+  if (!live) {  // dead lanes load node 0 (unconditional loads keep the gather free of branches)
+    q.base = 0;
+    q.sn = 0;
+  }
+  // box-relative coordinates
+  const int r0 = k * c0 - o0, r1 = k * c1 - o1, r2 = (D == 3) ? k * c2 - o2 : 0;
+  q.rn = ax0 ? r0 : (ax1 ? r1 : r2);
+  q.ra = (ax0 ? r1 : r0) + t1;
+  q.rb = (D == 3) ? (ax2 ? r1 : r2) + t2 : 0;
   q.ilo = half == 2 ? k + 1 : 0;
   q.ihi = half == 1 ? k : 2 * k;
   return q;
@@ -254,14 +260,13 @@ __device__ __forceinline__ VisitPrep prep_visit(Visit vis, bool live, int t1, in
 // No global atomics, and y needs no prior zeroing.
 // VJP: x = w drives du; u2 = u gives the order-wise reduction, counted on each face's primary visit.
 template <typename T, int D, int K, bool VJP>
-__global__ __launch_bounds__(kBoxThreads) void box_kernel(
+__device__ __forceinline__ void box_body(
     const T *__restrict__ x, const T *__restrict__ u2, T *__restrict__ y, T *__restrict__ halo,
     double *__restrict__ partial, const Box *__restrict__ boxes, const Visit *__restrict__ visits,
     const BoxLine *__restrict__ lines, const T *__restrict__ tab, int s0, int s1, int s2, int accumulate) {
   constexpr int k = K - 1, NN = 2 * k + 1;
   constexpr int TL = lines_per_face(D, k), FPB = kBoxThreads / TL, NT = TL * FPB;
-  constexpr int NB = box_nodes(D, k), P = box_pitch(D, k), ACC = box_acc(D, k);
-  constexpr int SY = P, SZ = P * NB;  // accumulator strides
+  constexpr int E = box_extent(D), ACC = box_acc(D);
   __shared__ T acc[ACC];
   __shared__ T sa[FPB * k * TL];  // per-face k x (k+1)^(d-1) values, transformed in place
   const T *g = tab;
@@ -279,26 +284,36 @@ __global__ __launch_bounds__(kBoxThreads) void box_kernel(
   const int line_first = __builtin_amdgcn_readfirstlane(bp->line_first);
   const int line_count = __builtin_amdgcn_readfirstlane(bp->line_count);
   const int tid = threadIdx.x;
-  for (int i = tid; i < ACC; i += kBoxThreads) acc[i] = T(0);
-  // Flush plan: a group of G lanes takes one touched x-line of the box, lane = box x coordinate, so
-  // the stores of a group are consecutive.  Accumulating applies need y at the exclusive nodes: load
-  // it now, the face work hides the latency.
-  constexpr int G = (D == 3) ? 16 : 64, kGroups = kBoxThreads / G, kPre = (D == 3) ? 8 : 4;
-  const int grp = tid / G, gx = tid % G;
   const int64_t box_base = (int64_t)o0 + (int64_t)s1 * o1 + (int64_t)s2 * o2;
-  T ypre[kPre];
+  // Flush plan: a group of E lanes takes touched x-lines grp, grp + kGroups, ... of the box, lane = box
+  // x coordinate, so the stores of a group are consecutive; kLines lines per group cover the box.
+  constexpr int kGroups = kBoxThreads / E, kLines = ACC / (E * kGroups);
+  static_assert(kGroups * kLines * E == ACC, "flush groups must cover the accumulator");
+  const int grp = tid / E, gx = tid % E;
+  const uint64_t gbit = (uint64_t)1 << gx;
+  // Issue every global load of the prologue before waiting on any: the box's lines, its first visits.
+  BoxLine bl[kLines];
+  const int lc1 = max(line_count - 1, 0);
 #pragma unroll
-  for (int m = 0; m < kPre; ++m) {
-    ypre[m] = T(0);
-    const int r = grp + m * kGroups;
-    if (accumulate && r < line_count) {
-      const BoxLine bl = lines[line_first + r];
-      const uint64_t bit = (uint64_t)1 << gx;
-      if ((bl.touched & bit) && !(bl.shared & bit)) {
-        const int ry = bl.line % NB, rz = bl.line / NB;
-        ypre[m] = y[box_base + gx + (int64_t)s1 * ry + (int64_t)s2 * rz];
-      }
-    }
+  for (int m = 0; m < kLines; ++m) bl[m] = lines[line_first + min(grp + m * kGroups, lc1)];
+  const int nv0 = min(visit_count, kVisitChunk);
+  const Visit v_first = visits[visit_first + min(tid, max(nv0 - 1, 0))];
+  for (int i = tid; i < ACC; i += kBoxThreads) acc[i] = T(0);
+  // Per line: fa = accumulator slot | shared flag << 12 (-1: the lane's node is not touched);
+  // fs = y offset from the box origin (exclusive node) or halo slot (shared node).
+  int fa[kLines], fs[kLines];
+  T yv[kLines];
+#pragma unroll
+  for (int m = 0; m < kLines; ++m) {
+    const bool touched = grp + m * kGroups < line_count && (bl[m].touched & gbit);
+    const bool sh = (bl[m].shared & gbit) != 0;
+    const int ry = bl[m].line % E, rz = bl[m].line / E;
+    fa[m] = touched ? (box_slot(D, gx, ry, rz) | (sh ? 1 << 12 : 0)) : -1;
+    fs[m] = sh ? bl[m].slot_base + __popcll(bl[m].shared & (gbit - 1)) : gx + s1 * ry + s2 * rz;
+  }
+  if (accumulate) {  // exclusive nodes start from y: their accumulator slot is seeded with it
+#pragma unroll
+    for (int m = 0; m < kLines; ++m) yv[m] = y[box_base + (fa[m] >= 0 && fa[m] < (1 << 12) ? fs[m] : 0)];
   }
   const int f = tid / TL, t = tid - f * TL;
   const bool in_block = tid < NT;
@@ -307,33 +322,41 @@ __global__ __launch_bounds__(kBoxThreads) void box_kernel(
   double pj[k];
 #pragma unroll
   for (int j = 0; j < k; ++j) pj[j] = 0.0;
-  __syncthreads();
 
   // The brick's visits are staged in LDS, and the gather of batch b+1 is issued before the work on
   // batch b, so global-memory latency overlaps the contractions, barriers and LDS accumulation.
   __shared__ Visit svis[kVisitChunk];
+  if (tid < nv0) svis[tid] = v_first;
+  __syncthreads();  // also orders the zeroing of acc before the seeding below
   for (int vc = 0; vc < visit_count; vc += kVisitChunk) {
     const int nv = min(visit_count - vc, kVisitChunk);
-    __syncthreads();
-    for (int i = tid; i < nv; i += kBoxThreads) svis[i] = visits[visit_first + vc + i];
-    __syncthreads();
+    if (vc > 0) {
+      __syncthreads();
+      for (int i = tid; i < nv; i += kBoxThreads) svis[i] = visits[visit_first + vc + i];
+      __syncthreads();
+    }
     VisitPrep nxt = prep_visit<D, K>(in_block && f < nv ? svis[f] : Visit(0), in_block && f < nv, t1, t2, s0, s1,
                                      s2, o0, o1, o2);
     T lnext[NN], unext[NN];
 #pragma unroll
     for (int i = 0; i < NN; ++i) {
-      lnext[i] = nxt.live ? x[nxt.base + i * nxt.sn] : T(0);
-      unext[i] = (VJP && nxt.live && nxt.prim) ? u2[nxt.base + i * nxt.sn] : T(0);
+      lnext[i] = x[nxt.base + i * nxt.sn];
+      if (VJP) unext[i] = u2[nxt.base + i * nxt.sn];
+    }
+    if (vc == 0 && accumulate) {  // seed; the barrier after the first contraction orders it before the adds
+#pragma unroll
+      for (int m = 0; m < kLines; ++m)
+        if (fa[m] >= 0 && fa[m] < (1 << 12)) acc[fa[m]] = yv[m];
     }
   for (int v0 = 0; v0 < nv; v0 += FPB) {
     const VisitPrep cur = nxt;
     const bool live = cur.live, prim = cur.prim;
-    const int an = cur.an, abase = cur.abase, ilo = cur.ilo, ihi = cur.ihi;
+    const int ilo = cur.ilo, ihi = cur.ihi;
     T line[NN], uline[NN];
 #pragma unroll
     for (int i = 0; i < NN; ++i) {
       line[i] = lnext[i];
-      uline[i] = unext[i];
+      uline[i] = VJP ? unext[i] : T(0);
     }
     if (v0 + FPB < nv) {  // issue the next batch's gather
       const int vi = v0 + FPB + f;
@@ -341,22 +364,47 @@ __global__ __launch_bounds__(kBoxThreads) void box_kernel(
                              o1, o2);
 #pragma unroll
       for (int i = 0; i < NN; ++i) {
-        lnext[i] = nxt.live ? x[nxt.base + i * nxt.sn] : T(0);
-        unext[i] = (VJP && nxt.live && nxt.prim) ? u2[nxt.base + i * nxt.sn] : T(0);
+        lnext[i] = x[nxt.base + i * nxt.sn];
+        if (VJP) unext[i] = u2[nxt.base + i * nxt.sn];
       }
     }
 
+    // normal contraction, folded with the reflection symmetry g_j[2k-i] = (-1)^(j+1) g_j[i]
+    // (order j+1 odd in this 0-based loop: symmetric rows use the sums, antisymmetric rows the differences)
     T a[k], au[k];
+    {
+      T ev[k], od[k], eu[k], ou[k];
 #pragma unroll
-    for (int j = 0; j < k; ++j) {
-      T s = T(0), su = T(0);
-#pragma unroll
-      for (int i = 0; i < NN; ++i) {
-        s = fma(g[j * NN + i], line[i], s);
-        if (VJP) su = fma(g[j * NN + i], uline[i], su);
+      for (int i = 0; i < k; ++i) {
+        ev[i] = line[i] + line[2 * k - i];
+        od[i] = line[i] - line[2 * k - i];
+        if (VJP) {
+          eu[i] = uline[i] + uline[2 * k - i];
+          ou[i] = uline[i] - uline[2 * k - i];
+        }
       }
-      a[j] = live ? s : T(0);
-      au[j] = (VJP && live && prim) ? su : T(0);
+#pragma unroll
+      for (int j = 0; j < k; ++j) {
+        T s, su = T(0);
+        if (j % 2 == 0) {
+          s = g[j * NN + k] * line[k];
+          if (VJP) su = g[j * NN + k] * uline[k];
+#pragma unroll
+          for (int i = 0; i < k; ++i) {
+            s = fma(g[j * NN + i], ev[i], s);
+            if (VJP) su = fma(g[j * NN + i], eu[i], su);
+          }
+        } else {
+          s = T(0);
+#pragma unroll
+          for (int i = 0; i < k; ++i) {
+            s = fma(g[j * NN + i], od[i], s);
+            if (VJP) su = fma(g[j * NN + i], ou[i], su);
+          }
+        }
+        a[j] = live ? s : T(0);
+        au[j] = (VJP && live && prim) ? su : T(0);
+      }
     }
     if (in_block) {
 #pragma unroll
@@ -415,13 +463,31 @@ __global__ __launch_bounds__(kBoxThreads) void box_kernel(
 #pragma unroll
     for (int j = 0; j < k; ++j) cj[j] = in_block ? res[(f * k + j) * TL + t] : T(0);
     if (live) {
+      // expansion y_i = sum_j gs_j[i] c_j, folded: E_i from the symmetric orders, O_i from the others
+      T yv[NN];
+#pragma unroll
+      for (int i = 0; i <= k; ++i) {
+        T e = T(0), o = T(0);
+#pragma unroll
+        for (int j = 0; j < k; ++j) {
+          if (j % 2 == 0)
+            e = fma(gs[j * NN + i], cj[j], e);
+          else if (i < k)
+            o = fma(gs[j * NN + i], cj[j], o);
+        }
+        yv[i] = e + o;
+        if (i < k) yv[2 * k - i] = e - o;
+      }
+      const int axis = cur.axis, rn = cur.rn, ra = cur.ra, rb = cur.rb;
 #pragma unroll
       for (int i = 0; i < NN; ++i) {
         if (i >= ilo && i <= ihi) {
-          T s = T(0);
-#pragma unroll
-          for (int j = 0; j < k; ++j) s = fma(gs[j * NN + i], cj[j], s);
-          __hip_atomic_fetch_add(&acc[abase + i * an], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          const int xn = rn + i;
+          const int bx0 = axis == 0 ? xn : ra;
+          const int by = axis == 1 ? xn : (axis == 0 ? ra : rb);
+          const int bz = axis == 2 ? xn : rb;
+          __hip_atomic_fetch_add(&acc[box_slot(D, bx0, by, D == 3 ? bz : 0)], yv[i], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
       if (VJP && prim) {
@@ -433,22 +499,15 @@ __global__ __launch_bounds__(kBoxThreads) void box_kernel(
   }
   }
 
-  // flush
-  for (int r = grp, m = 0; r < line_count; r += kGroups, ++m) {
-    const BoxLine bl = lines[line_first + r];
-    const uint64_t bit = (uint64_t)1 << gx;
-    if (!(bl.touched & bit)) continue;
-    const int ry = bl.line % NB, rz = bl.line / NB;
-    const T v = acc[gx + SY * ry + SZ * rz];
-    if (bl.shared & bit) {
-      halo[bl.slot_base + __popcll(bl.shared & (bit - 1))] = v;
-    } else {
-      T *p = y + box_base + gx + (int64_t)s1 * ry + (int64_t)s2 * rz;
-      T pv = T(0);
+  // flush: exclusive nodes to y, shared ones to their halo slot (no global loads here)
 #pragma unroll
-      for (int mm = 0; mm < kPre; ++mm)
-        if (mm == m) pv = ypre[mm];
-      *p = m < kPre ? pv + v : (accumulate ? *p + v : v);
+  for (int m = 0; m < kLines; ++m) {
+    if (fa[m] >= 0) {
+      const T v = acc[fa[m] & 0xFFF];
+      if (fa[m] >> 12)
+        halo[fs[m]] = v;
+      else
+        y[box_base + fs[m]] = v;
     }
   }
 
@@ -471,6 +530,28 @@ __global__ __launch_bounds__(kBoxThreads) void box_kernel(
     }
   }
 }
+
+#define GHOST_BOX_PARAMS                                                                                  \
+  const T *__restrict__ x, const T *__restrict__ u2, T *__restrict__ y, T *__restrict__ halo,             \
+      double *__restrict__ partial, const Box *__restrict__ boxes, const Visit *__restrict__ visits,      \
+      const BoxLine *__restrict__ lines, const T *__restrict__ tab, int s0, int s1, int s2, int accumulate
+#define GHOST_BOX_ARGS x, u2, y, halo, partial, boxes, visits, lines, tab, s0, s1, s2, accumulate
+
+// Two blocks of 512 threads per CU need at most 128 VGPRs (4 waves per SIMD); the compiler is held to
+// that where it fits without spilling (the apply up to k = 6).  The VJP and k = 7 carry more live
+// values and run one block per CU instead.
+template <typename T, int D, int K, bool VJP>
+__global__ __launch_bounds__(kBoxThreads) __attribute__((amdgpu_waves_per_eu(4))) void box_kernel(
+    GHOST_BOX_PARAMS) {
+  box_body<T, D, K, VJP>(GHOST_BOX_ARGS);
+}
+
+template <typename T, int D, int K, bool VJP>
+__global__ __launch_bounds__(kBoxThreads) void box_kernel_wide(GHOST_BOX_PARAMS) {
+  box_body<T, D, K, VJP>(GHOST_BOX_ARGS);
+}
+#undef GHOST_BOX_PARAMS
+#undef GHOST_BOX_ARGS
 
 // y[node] (+)= sum of the node's halo slots, for every support node on a shared box face.
 template <typename T>
@@ -589,18 +670,28 @@ hipError_t dispatch(const DevPlan &p, const T *x, const T *u2, T *y, double *par
 }
 
 
+template <typename T, int D, int K, bool VJP>
+void launch_box(const DevPlan &p, const T *x, const T *u2, T *y, T *halo, const T *tab, bool accumulate,
+                hipStream_t s) {
+  const dim3 grid(p.n_boxes), block(kBoxThreads);
+  if constexpr (VJP || K == 8)
+    hipLaunchKernelGGL((box_kernel_wide<T, D, K, VJP>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes,
+                       p.visits, p.box_lines, tab, p.stride[0], p.stride[1], p.stride[2], (int)accumulate);
+  else
+    hipLaunchKernelGGL((box_kernel<T, D, K, VJP>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes,
+                       p.visits, p.box_lines, tab, p.stride[0], p.stride[1], p.stride[2], (int)accumulate);
+}
+
 template <typename T, bool VJP>
 hipError_t dispatch_box(const DevPlan &p, const T *x, const T *u2, T *y, const T *tab, bool accumulate,
                         hipStream_t s) {
   if (p.n_boxes <= 0) return hipSuccess;
   T *halo = reinterpret_cast<T *>(p.halo);
-  const dim3 grid(p.n_boxes), block(kBoxThreads);
   hipError_t e = hipErrorInvalidValue;
-#define GHOST_BCASE(D_, K_)                                                                                    \
-  if (p.dim == D_ && p.k + 1 == K_) {                                                                         \
-    hipLaunchKernelGGL((box_kernel<T, D_, K_, VJP>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes, \
-                       p.visits, p.box_lines, tab, p.stride[0], p.stride[1], p.stride[2], (int)accumulate);    \
-    e = hipGetLastError();                                                                                     \
+#define GHOST_BCASE(D_, K_)                                           \
+  if (p.dim == D_ && p.k + 1 == K_) {                                 \
+    launch_box<T, D_, K_, VJP>(p, x, u2, y, halo, tab, accumulate, s); \
+    e = hipGetLastError();                                            \
   }
   GHOST_BCASE(2, 2) GHOST_BCASE(2, 3) GHOST_BCASE(2, 4) GHOST_BCASE(2, 5) GHOST_BCASE(2, 6) GHOST_BCASE(2, 7)
   GHOST_BCASE(2, 8) GHOST_BCASE(3, 2) GHOST_BCASE(3, 3) GHOST_BCASE(3, 4) GHOST_BCASE(3, 5) GHOST_BCASE(3, 6)

@@ -444,7 +444,7 @@ std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], dou
 
 std::string build_box_layout(Plan &p) {
   const int d = p.dim, k = p.k;
-  const int B = box_cells(d, k), NB = box_nodes(d, k), P = box_pitch(d, k);
+  const int B = box_cells(d, k), NB = box_nodes(d, k), E = box_extent(d);
   const int64_t kB = (int64_t)k * B;
   int nbr[3] = {1, 1, 1};
   for (int a = 0; a < d; ++a) nbr[a] = (p.n[a] + B - 1) / B;
@@ -487,7 +487,7 @@ std::string build_box_layout(Plan &p) {
   p.visits.clear();
   p.box_runs.clear();
   p.box_lines.clear();
-  if (NB > 64) return "box node extent exceeds the 64-bit line masks";
+  if (NB > E) return "box node extent exceeds the accumulator extent";
   struct HaloRef { int64_t node; int32_t slot; };
   std::vector<HaloRef> halo;
   int64_t slots = 0;
@@ -554,7 +554,7 @@ std::string build_box_layout(Plan &p) {
           e = xe;
         BoxRun br{};
         br.start = x + p.L[0] * line;
-        br.acc = (int32_t)(rx + P * (ry + (int64_t)NB * rz));
+        br.acc = (int32_t)(rx + E * (ry + (int64_t)E * rz));  // box-linear index (before the slot rotation)
         br.len = (int32_t)(e - x);
         br.slot = -1;
         if (node_shared) {
@@ -564,7 +564,7 @@ std::string build_box_layout(Plan &p) {
         }
         p.box_runs.push_back(br);
         // device line record (runs of one line are consecutive: start a record at a new line)
-        const int32_t lrel = (int32_t)(ry + (int64_t)NB * rz);
+        const int32_t lrel = (int32_t)(ry + (int64_t)E * rz);
         if (p.box_lines.size() == (size_t)bx.line_first || p.box_lines.back().line != lrel)
           p.box_lines.push_back(BoxLine{0, 0, lrel, (int32_t)(node_shared ? br.slot : slots)});
         BoxLine &bl = p.box_lines.back();
@@ -577,6 +577,10 @@ std::string build_box_layout(Plan &p) {
     }
     bx.run_count = (int32_t)(p.box_runs.size() - bx.run_first);
     bx.line_count = (int32_t)(p.box_lines.size() - bx.line_first);
+    // the kernel reads the first visit and line of every box unconditionally, and one lane group per
+    // box line: a box has at least one of each and at most one line per (y, z) of its node box
+    if (bx.visit_count < 1 || bx.line_count < 1 || bx.line_count > (d == 3 ? E * E : E))
+      return "box layout: a box without visits or lines, or with more lines than its node box";
     p.boxes.push_back(bx);
   }
   if (slots >= ((int64_t)1 << 31) || (int64_t)p.visits.size() >= ((int64_t)1 << 31))

@@ -42,7 +42,7 @@ struct Box {
 // (its value goes to halo slot slot_base + (number of shared bits below x) instead of y).
 struct BoxLine {
   uint64_t touched, shared;
-  int32_t line;        // ry + NB * rz (box-relative line coordinates)
+  int32_t line;        // ry + E * rz (box-relative line coordinates, E = box_extent)
   int32_t slot_base;
 };
 
@@ -53,7 +53,7 @@ using Visit = uint64_t;
 
 struct BoxRun {          // a run of touched box nodes along x
   int64_t start;         // lattice index of the first node
-  int32_t acc;           // accumulator index of the first node
+  int32_t acc;           // box-linear index x + E*(y + E*z) of the first node (E = box_extent)
   int32_t len;
   int32_t slot;          // -1: exclusive, written to y; else first halo slot of the run
   int32_t pad;

@@ -53,6 +53,25 @@ def test_tables_match_oracle(k):
     np.testing.assert_allclose(t["weights"], [float(x) for x in gll_weights(k)], rtol=0, atol=2e-16)
 
 
+@pytest.mark.parametrize("k", range(1, 8))
+def test_tables_reflection_symmetry_exact(k):
+    """Reflection about the face maps patch node i to 2k-i; the jump of the order-m derivative changes by
+    (-1)^(m+1) and the mass matrix is centro-symmetric.  The box kernel folds its contractions with these
+    identities, so the tables must satisfy them bit for bit (the oracle's vectors do up to rounding)."""
+    w = WORKLOADS["disk2d_q2_32"]
+    op = GhostOperator(2, w.n, w.lo, w.h, k, gamma_paper(k, w.h), centre=w.centre, radius=w.radius, device=-1)
+    t = op.tables()
+    J = np.asarray(t["jumps"])
+    for m in range(1, k + 1):
+        assert np.array_equal(J[m - 1][::-1], (-1) ** (m + 1) * J[m - 1])
+    M = np.asarray(t["mass"])
+    assert np.array_equal(M, M.T) and np.array_equal(M, M[::-1, ::-1])
+    J_or = opatch.jump_vectors_reference(k)
+    for m in range(1, k + 1):  # the oracle's (independent) vectors obey the same identity to rounding
+        v = np.array([float(x) for x in J_or[m]])
+        np.testing.assert_allclose(v[::-1], (-1) ** (m + 1) * v, rtol=0, atol=1e-13 * np.abs(v).max())
+
+
 @pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64"])
 def test_plan_matches_oracle(name):
     w = WORKLOADS[name]
@@ -189,7 +208,7 @@ def test_box_layout(name):
     """Box scatter layout: runs of all boxes cover the support exactly; a node is either exclusive to one
     box (written to y) or routed through halo slots by every box touching it; each face is visited once
     (whole patch) or twice (lower / upper cell, by the bricks of those cells); run accumulator indices
-    are the box-relative node coordinates."""
+    are the box-relative node coordinates, x + E*(y + E*z) with E the accumulator extent."""
     from paper_2503_00246_amd.workloads import Workload
     extra = {"small3d_q5_24": Workload("s", 3, 5, (24,) * 3, (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73),
              "small3d_q7_14": Workload("s", 3, 7, (14, 13, 12), (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)}
@@ -199,7 +218,8 @@ def test_box_layout(name):
     d, k = w.d, w.k
     B = 15 // k if d == 3 else 63 // k
     NB = k * B + 1
-    P = NB if NB % 2 else NB + 1
+    E = 16 if d == 3 else 64
+    assert NB <= E
     assert op.stats["brick"] == B
     L_ = np.array(list(w.lattice) + [1] * (3 - d))
     cls = omesh.classify_ball(w.n, w.lo, w.h, w.centre, w.radius)
@@ -225,7 +245,7 @@ def test_box_layout(name):
     rel = I - boxes[rbox, 0:3]
     assert np.all(rel >= 0) and np.all(rel[:, :d] < NB)
     accs = np.concatenate([np.arange(a_, a_ + n_) for _, a_, n_, _ in runs])
-    assert np.array_equal(accs, rel[:, 0] + P * (rel[:, 1] + NB * rel[:, 2]))
+    assert np.array_equal(accs, rel[:, 0] + E * (rel[:, 1] + E * rel[:, 2]))
     # visits
     v = visits.astype(np.uint64)
     c = np.stack([(v & 0xFFFFF), (v >> 20) & 0xFFFFF, (v >> 40) & 0xFFFFF], -1).astype(np.int64)
