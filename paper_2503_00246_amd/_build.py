@@ -20,6 +20,7 @@ LIB = os.path.join(PKG, "libghost.so")
 
 HOST_SOURCES = ["ghost_plan.cpp", "ghost_abi.cpp"]
 HIP_SOURCES = ["ghost_kernels.hip", "ghost_cg.hip"]
+GEN_SOURCE = "gen_tables.cpp"  # host program run at build time; writes _build/ghost_tables_gen.h
 
 
 def _hipcc():
@@ -31,7 +32,7 @@ def _hipcc():
 
 def _common():
     return ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
-            "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", BUILD]
 
 
 def _compile(src):
@@ -51,11 +52,27 @@ def _compile(src):
     return obj
 
 
+def _generate_tables(host_objs):
+    """Link and run gen_tables: the 1D tables as compile-time constants for the kernels."""
+    gen_obj = _compile(GEN_SOURCE)
+    exe = os.path.join(BUILD, "gen_tables")
+    plan_obj = [o for o in host_objs if os.path.basename(o).startswith("ghost_plan")]
+    cmd = [_hipcc(), "-o", exe, gen_obj] + plan_obj
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    r = subprocess.run([exe, os.path.join(BUILD, "ghost_tables_gen.h")], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"gen_tables failed\n{r.stdout}\n{r.stderr}")
+
+
 def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
-    srcs = HOST_SOURCES + HIP_SOURCES
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    with cf.ThreadPoolExecutor(max_workers=min(4, len(HOST_SOURCES))) as ex:
+        host_objs = list(ex.map(_compile, HOST_SOURCES))
+    _generate_tables(host_objs)
+    with cf.ThreadPoolExecutor(max_workers=min(4, len(HIP_SOURCES))) as ex:
+        objs = host_objs + list(ex.map(_compile, HIP_SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

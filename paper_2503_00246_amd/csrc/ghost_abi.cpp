@@ -111,6 +111,7 @@ void host_tables(const ghost_ctx *c, std::vector<double> &t64, std::vector<float
     t64[i] = p.jumps[i];
     t64[ghost::tab_gs(k) + i] = (c->gamma[j] * t64[ghost::tab_hscale(k) + j]) * p.jumps[i];
   }
+  for (int j = 0; j < k; ++j) t64[ghost::tab_coef(k) + j] = c->gamma[j] * t64[ghost::tab_hscale(k) + j];
   for (int i = 0; i < K * K; ++i) t64[ghost::tab_M(k) + i] = p.mass[i];
   for (int i = 0; i < K; ++i) t64[ghost::tab_gllw(k) + i] = p.weights[i];
   for (int i = 0; i < ghost::tab_size32(k); ++i) t32[i] = (float)t64[i];
@@ -246,14 +247,27 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
     const int32_t *hp = nullptr, *hs = nullptr;
     double *halo = nullptr;
     if (rc == GHOST_OK) rc = upload(c, p.boxes.data(), p.boxes.size(), const_cast<ghost::Box **>(&bxv));
-    if (rc == GHOST_OK) rc = upload(c, p.visits.data(), p.visits.size(), const_cast<ghost::Visit **>(&vv));
-    if (rc == GHOST_OK) rc = upload(c, p.box_lines.data(), p.box_lines.size(), const_cast<ghost::BoxLine **>(&rv));
+    {
+      // the box kernel copies visits and line records in 16-byte pieces: pad both arrays by one piece
+      std::vector<ghost::Visit> vpad(p.visits);
+      vpad.resize(vpad.size() + 2, 0);
+      std::vector<ghost::BoxLine> lpad(p.box_lines);
+      lpad.push_back(ghost::BoxLine{});
+      if (rc == GHOST_OK) rc = upload(c, vpad.data(), vpad.size(), const_cast<ghost::Visit **>(&vv));
+      if (rc == GHOST_OK) rc = upload(c, lpad.data(), lpad.size(), const_cast<ghost::BoxLine **>(&rv));
+    }
     if (rc == GHOST_OK) rc = upload(c, p.halo_node.data(), p.halo_node.size(), const_cast<int64_t **>(&hn));
     if (rc == GHOST_OK) rc = upload(c, p.halo_ptr.data(), p.halo_ptr.size(), const_cast<int32_t **>(&hp));
     if (rc == GHOST_OK) rc = upload(c, p.halo_slot.data(), p.halo_slot.size(), const_cast<int32_t **>(&hs));
     if (rc == GHOST_OK) rc = upload<double>(c, nullptr, (size_t)std::max<int64_t>(1, p.n_slots), &halo);
     if (rc == GHOST_OK)
       rc = upload<double>(c, nullptr, (size_t)std::max(1, std::max(d.n_batches, d.n_boxes)) * k, &d.vjp_partial);
+    const ghost::BoxSched sched0{};
+    if (rc == GHOST_OK) rc = upload(c, &sched0, 1, &d.sched);
+    if (rc == GHOST_OK) {
+      const hipError_t ea = hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, device);
+      if (ea != hipSuccess) rc = fail_hip(ea, "hipDeviceGetAttribute");
+    }
     d.boxes = bxv;
     d.visits = vv;
     d.box_lines = rv;

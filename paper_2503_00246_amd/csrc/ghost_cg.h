@@ -8,11 +8,6 @@
 
 namespace ghost {
 
-struct GammaArg {
-  double v[kMaxDegree];
-};
-hipError_t launch_set_gamma_host(const DevPlan &p, GammaArg g, hipStream_t s);
-
 struct CgWork;
 void cg_free(CgWork *w);
 int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &opts, ghost_cg_result &res,

@@ -177,23 +177,9 @@ __global__ void reduce_kernel(const double *partial, int n, double *scal, int mo
   }
 }
 
-__global__ void set_gamma_host_kernel(GammaArg g, int k, double *tab64, float *tab32) {
-  const int NN = 2 * k + 1;
-  const double *hscale = tab64 + 2 * k * NN + (k + 1) * (k + 1);
-  for (int idx = threadIdx.x; idx < k * NN; idx += blockDim.x) {
-    const int j = idx / NN;
-    const double v = (g.v[j] * hscale[j]) * tab64[idx];
-    tab64[k * NN + idx] = v;
-    tab32[k * NN + idx] = (float)v;
-  }
-}
 
 }  // namespace
 
-hipError_t launch_set_gamma_host(const DevPlan &p, GammaArg g, hipStream_t s) {
-  hipLaunchKernelGGL(set_gamma_host_kernel, dim3(1), dim3(128), 0, s, g, p.k, p.tab64, p.tab32);
-  return hipGetLastError();
-}
 
 struct CgWork {
   Run *segs = nullptr;

@@ -10,18 +10,27 @@
 namespace ghost {
 
 // Layout of the per-context table buffers (offsets in elements of the precision):
-//   [0, k*NN)            g   : reference jump vectors, row j-1 = order j
-//   [k*NN, 2*k*NN)       gs  : gamma_j h^{d-1-2j} g_j, the expansion coefficients of one face
-//   [2*k*NN, +K*K)       M   : reference mass matrix
+//   [0, k*NN)            g    : reference jump vectors, row j-1 = order j
+//   [k*NN, 2*k*NN)       gs   : gamma_j h^{d-1-2j} g_j, the expansion coefficients of one face
+//   [2*k*NN, +K*K)       M    : reference mass matrix
+//   [.., +k)             coef : gamma_j h^{d-1-2j}
 //   FP64 buffer only: [.., +k) hscale_j = h^{d-1-2j}, then [.., +K) GLL weights on [0, 1]
-inline int tab_gs(int k) { return k * (2 * k + 1); }
-inline int tab_M(int k) { return 2 * k * (2 * k + 1); }
-inline int tab_hscale(int k) { return 2 * k * (2 * k + 1) + (k + 1) * (k + 1); }
-inline int tab_gllw(int k) { return tab_hscale(k) + k; }
-inline int tab_size64(int k) { return tab_gllw(k) + k + 1; }
-inline int tab_size32(int k) { return tab_hscale(k); }
+__host__ __device__ constexpr int tab_gs(int k) { return k * (2 * k + 1); }
+__host__ __device__ constexpr int tab_M(int k) { return 2 * k * (2 * k + 1); }
+__host__ __device__ constexpr int tab_coef(int k) { return tab_M(k) + (k + 1) * (k + 1); }
+__host__ __device__ constexpr int tab_hscale(int k) { return tab_coef(k) + k; }
+__host__ __device__ constexpr int tab_gllw(int k) { return tab_hscale(k) + k; }
+__host__ __device__ constexpr int tab_size64(int k) { return tab_gllw(k) + k + 1; }
+__host__ __device__ constexpr int tab_size32(int k) { return tab_hscale(k); }
 
 enum class Scatter { Owner = 0, Atomic = 1, Coloured = 2 };
+
+// Ticket counters of the persistent box kernel, one pair per scheduling group; zero between launches.
+constexpr int kSchedGroups = 8;
+struct BoxSched {
+  int ctr[kSchedGroups];
+  int done[kSchedGroups];
+};
 
 struct DevPlan {
   int dim = 0, k = 0;
@@ -54,6 +63,8 @@ struct DevPlan {
   const int32_t *halo_ptr = nullptr;
   const int32_t *halo_slot = nullptr;
   int n_halo = 0;
+  BoxSched *sched = nullptr;          // zero-initialised at setup
+  int n_cu = 0;                       // compute units of the device
 
   double *tab64 = nullptr;
   float *tab32 = nullptr;
@@ -65,6 +76,10 @@ hipError_t launch_apply_f32(const DevPlan &p, const float *u, float *y, bool acc
 hipError_t launch_vjp(const DevPlan &p, const double *u, const double *w, double *du, double *dgamma,
                       bool accumulate, hipStream_t s);
 hipError_t launch_set_gamma(const DevPlan &p, const double *gamma_dev, hipStream_t s);
+struct GammaArg {  // gamma by value, for host-side updates
+  double v[kMaxDegree];
+};
+hipError_t launch_set_gamma_host(const DevPlan &p, GammaArg g, hipStream_t s);
 hipError_t launch_mass_diag(const DevPlan &p, double *diag, hipStream_t s);
 
 }  // namespace ghost

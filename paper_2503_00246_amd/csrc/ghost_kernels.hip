@@ -26,7 +26,10 @@
 // between neighbouring patches.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ghost_device.h"
+#include "ghost_tables_gen.h"
 
 namespace ghost {
 namespace {
@@ -207,335 +210,453 @@ __global__ __launch_bounds__(kBlockThreads) void face_kernel(
 
 
 
-constexpr int kVisitChunk = 256;
-constexpr int kBoxThreads = 512;  // box kernel block size: 2 x the faces of a 256-thread batch in flight
 
-
-// Per-thread view of one face visit in a box: lattice address of the thread's normal line, the normal
-// stride, the line's box coordinates and the expanded plane range.
+// Per-thread view of one face visit in a box.
 struct VisitPrep {
-  int64_t base;          // lattice index of the thread's normal line, patch plane 0
-  int sn;                // lattice stride along the normal
-  int axis, rn, ra, rb;  // normal axis; box coordinates: normal origin, tangential a / b of the line
-  int ilo, ihi;          // expanded patch planes
+  uint32_t gofs;   // offset (elements) of the thread's normal line, patch plane 0, from the gather base
+  uint32_t sn;     // lattice stride along the normal (0 for dead lanes: they read the gather base)
+  int acc0, dacc;  // FP64 accumulator byte offset of the line at patch plane 0, byte stride along the normal
+  bool lo, hi;     // expand patch planes 0..k / k+1..2k
   bool live, prim;
 };
 
+// glo: offset of the gather base from the box origin (<= 0), so that every gathered offset is >= 0.
 template <int D, int K>
-__device__ __forceinline__ VisitPrep prep_visit(Visit vis, bool live, int t1, int t2, int s0, int s1, int s2,
-                                                int o0, int o1, int o2) {
-  constexpr int k = K - 1;
+__device__ __forceinline__ VisitPrep prep_visit(Visit vis, bool live, int t1, int t2, int s1, int s2, int o0,
+                                                int o1, int o2, int glo) {
+  constexpr int k = K - 1, E = box_extent(D), P = box_pitch(D);
   VisitPrep q;
-  q.live = live;
   const int c0 = (int)(vis & 0xFFFFF), c1 = (int)((vis >> 20) & 0xFFFFF), c2 = (int)((vis >> 40) & 0xFFFFF);
-  const int axis = (int)((vis >> 60) & 3);
-  const int half = (int)((vis >> 62) & 3);
-  q.axis = axis;
-  q.prim = half != 2;
-  const bool ax0 = axis == 0, ax1 = axis == 1, ax2 = axis == 2;
-  // lattice strides along the normal and the tangential axes (ta < tb)
-  q.sn = ax0 ? s0 : (ax1 ? s1 : s2);
-  const int st1 = ax0 ? s1 : s0;
-  const int st2 = (D == 3) ? (ax2 ? s1 : s2) : 0;
-  q.base = (int64_t)k * ((int64_t)c0 * s0 + (int64_t)c1 * s1 + (int64_t)c2 * s2) + (int64_t)(t1 * st1 + t2 * st2);
-  if (!live) {  // dead lanes load node 0 (unconditional loads keep the gather free of branches)
-    q.base = 0;
-    q.sn = 0;
+  const int axis = (int)((vis >> 60) & 3), half = (int)((vis >> 62) & 3);
+  // box coordinates of the line at patch plane 0: lower cell's first node plus the tangential offsets
+  // (tangential axes in increasing order: t1 along the first, t2 along the second)
+  int bx = k * c0 - o0, by = k * c1 - o1, bz = (D == 3) ? k * c2 - o2 : 0;
+  if (D == 3) {
+    bx += axis != 0 ? t1 : 0;
+    by += axis == 0 ? t1 : (axis == 2 ? t2 : 0);
+    bz += axis != 2 ? t2 : 0;
+  } else {
+    bx += axis == 1 ? t1 : 0;
+    by += axis == 0 ? t1 : 0;
   }
-  // box-relative coordinates
-  const int r0 = k * c0 - o0, r1 = k * c1 - o1, r2 = (D == 3) ? k * c2 - o2 : 0;
-  q.rn = ax0 ? r0 : (ax1 ? r1 : r2);
-  q.ra = (ax0 ? r1 : r0) + t1;
-  q.rb = (D == 3) ? (ax2 ? r1 : r2) + t2 : 0;
-  q.ilo = half == 2 ? k + 1 : 0;
-  q.ihi = half == 1 ? k : 2 * k;
+  q.live = live;
+  q.prim = half != 2;
+  q.gofs = live ? (uint32_t)(bx + s1 * by + s2 * bz - glo) : 0u;
+  q.sn = live ? (uint32_t)(axis == 0 ? 1 : (axis == 1 ? s1 : s2)) : 0u;
+  q.acc0 = (int)sizeof(double) * (bx + P * (by + E * bz));
+  q.dacc = (int)sizeof(double) * (axis == 0 ? 1 : (axis == 1 ? P : P * E));
+  q.lo = half != 2;
+  q.hi = half != 1;
   return q;
 }
 
-// Box apply (default scatter).  Workgroup = one brick of cells; it runs the per-face pipeline of
-// face_kernel over every face with a cell in the brick, expanding only into the brick's cells (a face
+template <int D>
+using LineMask = typename std::conditional<D == 3, uint32_t, uint64_t>::type;
+__device__ __forceinline__ int popc_mask(uint32_t m) { return __popc(m); }
+__device__ __forceinline__ int popc_mask(uint64_t m) { return __popcll(m); }
+
+// Dynamic box scheduling.  The blocks of a launch form up to kSchedGroups groups (blockIdx mod the
+// group count: the XCD a block runs on when workgroups are dispatched round-robin over the XCDs);
+// group x takes the boxes of one contiguous range of the brick order, one ticket at a time from its
+// counter.  A block stops after its first ticket past the range; the last block of a group to do so
+// resets the group's counters, so every launch starts from zero.
+// An LDS address as the LDS address space pointer the copy builtin takes.
+__device__ __forceinline__ __attribute__((address_space(3))) void *lds_ptr(char *p) {
+  return (__attribute__((address_space(3))) void *)p;
+}
+
+// s_waitcnt immediate: vector-memory count 0, the other counters left at their maximum.
+constexpr int kWaitVmcnt0 = (7 << 4) | (15 << 8);
+
+__device__ __forceinline__ int take_box(BoxSched *s, int grp, int lo, int hi, int nblk) {
+  const int t = atomicAdd(&s->ctr[grp], 1);
+  if (lo + t < hi) return lo + t;
+  if (atomicAdd(&s->done[grp], 1) == nblk - 1) {
+    atomicExch(&s->ctr[grp], 0);
+    atomicExch(&s->done[grp], 0);
+  }
+  return -1;
+}
+
+// Lattice index of a box's origin, and the offset (<= 0) from it of the gather base: the lowest node a
+// visit of the box can read is one cell below the box along some axis; gathers use 32-bit offsets
+// from that base.
+__device__ __forceinline__ int gather_low(int o0, int o1, int o2, int k, int s1, int s2, int64_t &base) {
+  base = (int64_t)o0 + (int64_t)s1 * o1 + (int64_t)s2 * o2;
+  const int64_t reach = (int64_t)k * (1 + s1 + s2);
+  return -(int)(base < reach ? base : reach);
+}
+
+// Box fields as wave-uniform scalars.
+struct BoxScalars {
+  int o0, o1, o2, visit_first, visit_count, line_first, line_count;
+};
+__device__ __forceinline__ BoxScalars load_box(const Box *__restrict__ boxes, int b) {
+  const Box *bp = boxes + __builtin_amdgcn_readfirstlane(b);
+  BoxScalars r;
+  r.o0 = __builtin_amdgcn_readfirstlane(bp->org[0]);
+  r.o1 = __builtin_amdgcn_readfirstlane(bp->org[1]);
+  r.o2 = __builtin_amdgcn_readfirstlane(bp->org[2]);
+  r.visit_first = __builtin_amdgcn_readfirstlane(bp->visit_first);
+  r.visit_count = __builtin_amdgcn_readfirstlane(bp->visit_count);
+  r.line_first = __builtin_amdgcn_readfirstlane(bp->line_first);
+  r.line_count = __builtin_amdgcn_readfirstlane(bp->line_count);
+  return r;
+}
+
+// Box apply (default scatter).  A box is (part of) one brick of cells: the kernel runs the per-face
+// pipeline of face_kernel over the box's face visits, expanding only into the brick's cells (a face
 // split between two bricks is visited twice, once per half), and sums the results in a dense LDS
-// accumulator over the brick's node box.  Nodes that no other box contains are then written to y
-// with plain stores; nodes on shared box faces go to halo slots that halo_kernel adds into y.
-// No global atomics, and y needs no prior zeroing.
-// VJP: x = w drives du; u2 = u gives the order-wise reduction, counted on each face's primary visit.
+// accumulator over the brick's node box (odd row pitch, so the lanes of a face spread over the banks).
+// Nodes that no other box touches are then written to y with plain stores; the others go to halo
+// slots that halo_kernel adds into y.  No global atomics on y, and y needs no prior zeroing.
+// The workgroups are persistent: each takes boxes from the scheduler and, while it works on one box,
+// already loads the next box's visits and line records and issues the gather of its first batch, so
+// that only the first box of a workgroup waits on memory before computing.
+// VJP: x = w drives du; u2 = u gives the order-wise reduction, counted on each face's primary visit,
+// and stored per box so that the reduction order does not depend on the schedule.
 template <typename T, int D, int K, bool VJP>
 __device__ __forceinline__ void box_body(
     const T *__restrict__ x, const T *__restrict__ u2, T *__restrict__ y, T *__restrict__ halo,
     double *__restrict__ partial, const Box *__restrict__ boxes, const Visit *__restrict__ visits,
-    const BoxLine *__restrict__ lines, const T *__restrict__ tab, int s0, int s1, int s2, int accumulate) {
+    const BoxLine *__restrict__ lines, const T *__restrict__ tab, int s1, int s2, int accumulate, int n_boxes,
+    BoxSched *__restrict__ sched) {
   constexpr int k = K - 1, NN = 2 * k + 1;
   constexpr int TL = lines_per_face(D, k), FPB = kBoxThreads / TL, NT = TL * FPB;
-  constexpr int E = box_extent(D), ACC = box_acc(D);
-  __shared__ T acc[ACC];
+  constexpr int E = box_extent(D), P = box_pitch(D), ACC = box_acc(D);
+  constexpr int kLinesMax = D == 3 ? E * E : E;
+  // jump vectors and mass matrix as compile-time constants (folded into the instructions); only the
+  // gamma-dependent factors coef_j = gamma_j h^{d-1-2j} come from the table buffer
+  using Tab = gen::Tab1d<K>;
+  T coef[k];
+#pragma unroll
+  for (int j = 0; j < k; ++j) coef[j] = tab[tab_coef(k) + j];
+  // The accumulator is FP64 in both precisions: LDS adds of doubles are served at a far higher rate
+  // than adds of floats on this hardware, and the FP32 path gains the exact summation of its
+  // contributions.
+  using A = double;
+  __shared__ A acc[ACC];
   __shared__ T sa[FPB * k * TL];  // per-face k x (k+1)^(d-1) values, transformed in place
-  const T *g = tab;
-  const T *gs = tab + k * NN;
-  const T *M = tab + 2 * k * NN;
-
-  const int bi = xcd_remap(blockIdx.x, gridDim.x);
-  // box fields as wave-uniform scalars (kept in SGPRs)
-  const Box *bp = boxes + bi;
-  const int o0 = __builtin_amdgcn_readfirstlane(bp->org[0]);
-  const int o1 = __builtin_amdgcn_readfirstlane(bp->org[1]);
-  const int o2 = __builtin_amdgcn_readfirstlane(bp->org[2]);
-  const int visit_first = __builtin_amdgcn_readfirstlane(bp->visit_first);
-  const int visit_count = __builtin_amdgcn_readfirstlane(bp->visit_count);
-  const int line_first = __builtin_amdgcn_readfirstlane(bp->line_first);
-  const int line_count = __builtin_amdgcn_readfirstlane(bp->line_count);
+  __shared__ Visit svis[2][kMaxBoxVisits];  // visits of the current box and of the next one
+  __shared__ BoxLine slines[kLinesMax];     // line records of the current box, then of the next one
+  __shared__ int s_box[2];
+  char *const accb = reinterpret_cast<char *>(acc);
   const int tid = threadIdx.x;
-  const int64_t box_base = (int64_t)o0 + (int64_t)s1 * o1 + (int64_t)s2 * o2;
-  // Flush plan: a group of E lanes takes touched x-lines grp, grp + kGroups, ... of the box, lane = box
-  // x coordinate, so the stores of a group are consecutive; kLines lines per group cover the box.
-  constexpr int kGroups = kBoxThreads / E, kLines = ACC / (E * kGroups);
-  static_assert(kGroups * kLines * E == ACC, "flush groups must cover the accumulator");
-  const int grp = tid / E, gx = tid % E;
-  const uint64_t gbit = (uint64_t)1 << gx;
-  // Issue every global load of the prologue before waiting on any: the box's lines, its first visits.
-  BoxLine bl[kLines];
-  const int lc1 = max(line_count - 1, 0);
-#pragma unroll
-  for (int m = 0; m < kLines; ++m) bl[m] = lines[line_first + min(grp + m * kGroups, lc1)];
-  const int nv0 = min(visit_count, kVisitChunk);
-  const Visit v_first = visits[visit_first + min(tid, max(nv0 - 1, 0))];
-  for (int i = tid; i < ACC; i += kBoxThreads) acc[i] = T(0);
-  // Per line: fa = accumulator slot | shared flag << 12 (-1: the lane's node is not touched);
-  // fs = y offset from the box origin (exclusive node) or halo slot (shared node).
-  int fa[kLines], fs[kLines];
-  T yv[kLines];
-#pragma unroll
-  for (int m = 0; m < kLines; ++m) {
-    const bool touched = grp + m * kGroups < line_count && (bl[m].touched & gbit);
-    const bool sh = (bl[m].shared & gbit) != 0;
-    const int ry = bl[m].line % E, rz = bl[m].line / E;
-    fa[m] = touched ? (box_slot(D, gx, ry, rz) | (sh ? 1 << 12 : 0)) : -1;
-    fs[m] = sh ? bl[m].slot_base + __popcll(bl[m].shared & (gbit - 1)) : gx + s1 * ry + s2 * rz;
-  }
-  if (accumulate) {  // exclusive nodes start from y: their accumulator slot is seeded with it
-#pragma unroll
-    for (int m = 0; m < kLines; ++m) yv[m] = y[box_base + (fa[m] >= 0 && fa[m] < (1 << 12) ? fs[m] : 0)];
-  }
+
+  // scheduling group and its box range
+  const int nblocks = gridDim.x, ng = min(kSchedGroups, nblocks), sg = blockIdx.x % ng;
+  const int nblk = nblocks / ng + (sg < nblocks % ng ? 1 : 0);
+  const int lo = (int)((int64_t)n_boxes * sg / ng), hi = (int)((int64_t)n_boxes * (sg + 1) / ng);
+
+  // per-thread constants: face slot and tangential line of the face pipeline, flush lane group
   const int f = tid / TL, t = tid - f * TL;
   const bool in_block = tid < NT;
   const int t1 = (D == 3) ? t % K : t;
   const int t2 = (D == 3) ? t / K : 0;
-  double pj[k];
-#pragma unroll
-  for (int j = 0; j < k; ++j) pj[j] = 0.0;
+  // Flush plan: a group of E lanes takes touched x-lines grp, grp + kGroups, ... of the box, lane = box
+  // x coordinate, so the stores of a group are consecutive; kLines lines per group cover the box.
+  constexpr int kGroups = kBoxThreads / E, kLines = kLinesMax / kGroups;
+  static_assert(kGroups * kLines == kLinesMax, "flush groups must cover the box lines");
+  const int grp = tid / E, gx = tid % E;
+  using Mask = LineMask<D>;
+  const Mask gbit = (Mask)1 << gx;
 
-  // The brick's visits are staged in LDS, and the gather of batch b+1 is issued before the work on
-  // batch b, so global-memory latency overlaps the contractions, barriers and LDS accumulation.
-  __shared__ Visit svis[kVisitChunk];
-  if (tid < nv0) svis[tid] = v_first;
-  __syncthreads();  // also orders the zeroing of acc before the seeding below
-  for (int vc = 0; vc < visit_count; vc += kVisitChunk) {
-    const int nv = min(visit_count - vc, kVisitChunk);
-    if (vc > 0) {
-      __syncthreads();
-      for (int i = tid; i < nv; i += kBoxThreads) svis[i] = visits[visit_first + vc + i];
-      __syncthreads();
-    }
-    VisitPrep nxt = prep_visit<D, K>(in_block && f < nv ? svis[f] : Visit(0), in_block && f < nv, t1, t2, s0, s1,
-                                     s2, o0, o1, o2);
-    T lnext[NN], unext[NN];
+  // first two boxes of this workgroup
+  if (tid == 0) {
+    const int b0 = take_box(sched, sg, lo, hi, nblk);
+    s_box[0] = b0;
+    s_box[1] = b0 >= 0 ? take_box(sched, sg, lo, hi, nblk) : -1;
+  }
+  __syncthreads();
+  int cur = __builtin_amdgcn_readfirstlane(s_box[0]);
+  int nxt = __builtin_amdgcn_readfirstlane(s_box[1]);
+  if (cur < 0) return;
+  BoxScalars bc = load_box(boxes, cur);
+  if (tid < bc.visit_count) svis[0][tid] = visits[bc.visit_first + tid];
+  if (tid < bc.line_count) slines[tid] = lines[bc.line_first + tid];
+  __syncthreads();
+  int64_t box_base;
+  int glo = gather_low(bc.o0, bc.o1, bc.o2, k, s1, s2, box_base);
+  VisitPrep nxp = prep_visit<D, K>(in_block && f < bc.visit_count ? svis[0][f] : Visit(0),
+                                   in_block && f < bc.visit_count, t1, t2, s1, s2, bc.o0, bc.o1, bc.o2, glo);
+  T lnext[NN], unext[NN];
+  {
+    const T *xg = x + (box_base + glo);
+    const T *ug = VJP ? u2 + (box_base + glo) : nullptr;
 #pragma unroll
     for (int i = 0; i < NN; ++i) {
-      lnext[i] = x[nxt.base + i * nxt.sn];
-      if (VJP) unext[i] = u2[nxt.base + i * nxt.sn];
+      lnext[i] = xg[nxp.gofs + i * nxp.sn];
+      if (VJP) unext[i] = ug[nxp.gofs + i * nxp.sn];
     }
-    if (vc == 0 && accumulate) {  // seed; the barrier after the first contraction orders it before the adds
+  }
+  int buf = 0;
+
+  for (;;) {
+    // ---- box `cur`: its visits are in svis[buf], its line records in slines, and the gather of its
+    // first batch is in flight in lnext / unext
+    T *const yb = y + box_base;
+    BoxScalars bn{};
+    int64_t nbase = 0;
+    int nglo = 0;
+    if (nxt >= 0) {
+      bn = load_box(boxes, nxt);
+      nglo = gather_low(bn.o0, bn.o1, bn.o2, k, s1, s2, nbase);
+    }
+    for (int i = tid; i < ACC; i += kBoxThreads) acc[i] = A(0);
+    // Per flush line: fa = accumulator byte offset | shared << 16 (-1: the lane's node is not touched);
+    // fs = y offset from the box origin (exclusive node) or halo slot (shared node).
+    int fa[kLines], fs[kLines];
 #pragma unroll
-      for (int m = 0; m < kLines; ++m)
-        if (fa[m] >= 0 && fa[m] < (1 << 12)) acc[fa[m]] = yv[m];
+    for (int m = 0; m < kLines; ++m) {
+      const BoxLine bl = slines[grp + m * kGroups];
+      const Mask tm = (Mask)bl.touched, sm = (Mask)bl.shared;
+      const bool touched = grp + m * kGroups < bc.line_count && (tm & gbit);
+      const bool sh = (sm & gbit) != 0;
+      const int ry = bl.line % E, rz = bl.line / E;
+      fa[m] = touched ? ((int)sizeof(A) * (gx + P * bl.line) | (sh ? 1 << 16 : 0)) : -1;
+      fs[m] = sh ? bl.slot_base + popc_mask(sm & (gbit - 1)) : gx + s1 * ry + s2 * rz;
     }
-  for (int v0 = 0; v0 < nv; v0 += FPB) {
-    const VisitPrep cur = nxt;
-    const bool live = cur.live, prim = cur.prim;
-    const int ilo = cur.ilo, ihi = cur.ihi;
-    T line[NN], uline[NN];
+    double pj[k];
 #pragma unroll
-    for (int i = 0; i < NN; ++i) {
-      line[i] = lnext[i];
-      uline[i] = VJP ? unext[i] : T(0);
+    for (int j = 0; j < k; ++j) pj[j] = 0.0;
+    int after = -1;  // the box after `nxt` (thread 0)
+    if (tid == 0 && nxt >= 0) after = take_box(sched, sg, lo, hi, nblk);
+    __syncthreads();  // acc zeroed before any add; slines read before it is refilled
+    // Copy the next box's visits and line records straight from global memory into LDS (16 bytes per
+    // lane, no registers held); the last batch of this box waits for the copies before its barrier.
+    // The global arrays are padded so that the last 16-byte piece stays inside them.
+    if (nxt >= 0) {
+      constexpr int kVisitPieces = kMaxBoxVisits * (int)sizeof(Visit) / 16;
+      constexpr int kLinePieces = kLinesMax * (int)sizeof(BoxLine) / 16;
+      const int vp = (bn.visit_count * (int)sizeof(Visit) + 15) / 16;
+      const int lp = (bn.line_count * (int)sizeof(BoxLine) + 15) / 16;
+      const int wbase = tid & ~63;
+      if (wbase < kVisitPieces && tid < vp)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(visits + bn.visit_first) + 16 * tid,
+                                         lds_ptr(reinterpret_cast<char *>(&svis[buf ^ 1][0]) + 16 * wbase), 16, 0, 0);
+      if (wbase < kLinePieces && tid < lp)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(lines + bn.line_first) + 16 * tid,
+                                         lds_ptr(reinterpret_cast<char *>(&slines[0]) + 16 * wbase), 16, 0, 0);
     }
-    if (v0 + FPB < nv) {  // issue the next batch's gather
-      const int vi = v0 + FPB + f;
-      nxt = prep_visit<D, K>(in_block && vi < nv ? svis[vi] : Visit(0), in_block && vi < nv, t1, t2, s0, s1, s2, o0,
-                             o1, o2);
+    T yv[kLines];
+    const int nbat = (bc.visit_count + FPB - 1) / FPB;
+    for (int b = 0; b < nbat; ++b) {
+      const VisitPrep cur_p = nxp;
+      const bool last = b + 1 == nbat;
+      T line[NN], uline[NN];
 #pragma unroll
       for (int i = 0; i < NN; ++i) {
-        lnext[i] = x[nxt.base + i * nxt.sn];
-        if (VJP) unext[i] = u2[nxt.base + i * nxt.sn];
+        line[i] = lnext[i];
+        uline[i] = VJP ? unext[i] : T(0);
       }
-    }
+      // the copies of the next box's records land before the barrier that precedes their use
+      if (last) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
 
-    // normal contraction, folded with the reflection symmetry g_j[2k-i] = (-1)^(j+1) g_j[i]
-    // (order j+1 odd in this 0-based loop: symmetric rows use the sums, antisymmetric rows the differences)
-    T a[k], au[k];
-    {
-      T ev[k], od[k], eu[k], ou[k];
+      // normal contraction a_j = g_j . line, folded with the reflection symmetry g_j[2k-i] = (-1)^(j+1)
+      // g_j[i] (derivative order j+1 odd for even j here: those rows use the sums, the others the
+      // differences); rows of dead faces are computed on node-0 data and never expanded
+      T a[k], au[k];
+      {
+        T ev[k], od[k], eu[k], ou[k];
 #pragma unroll
-      for (int i = 0; i < k; ++i) {
-        ev[i] = line[i] + line[2 * k - i];
-        od[i] = line[i] - line[2 * k - i];
-        if (VJP) {
-          eu[i] = uline[i] + uline[2 * k - i];
-          ou[i] = uline[i] - uline[2 * k - i];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < k; ++j) {
-        T s, su = T(0);
-        if (j % 2 == 0) {
-          s = g[j * NN + k] * line[k];
-          if (VJP) su = g[j * NN + k] * uline[k];
-#pragma unroll
-          for (int i = 0; i < k; ++i) {
-            s = fma(g[j * NN + i], ev[i], s);
-            if (VJP) su = fma(g[j * NN + i], eu[i], su);
-          }
-        } else {
-          s = T(0);
-#pragma unroll
-          for (int i = 0; i < k; ++i) {
-            s = fma(g[j * NN + i], od[i], s);
-            if (VJP) su = fma(g[j * NN + i], ou[i], su);
+        for (int i = 0; i < k; ++i) {
+          ev[i] = line[i] + line[2 * k - i];
+          od[i] = line[i] - line[2 * k - i];
+          if (VJP) {
+            eu[i] = uline[i] + uline[2 * k - i];
+            ou[i] = uline[i] - uline[2 * k - i];
           }
         }
-        a[j] = live ? s : T(0);
-        au[j] = (VJP && live && prim) ? su : T(0);
-      }
-    }
-    if (in_block) {
-#pragma unroll
-      for (int j = 0; j < k; ++j) sa[(f * k + j) * TL + t] = a[j];
-    }
-    __syncthreads();
-    // tangential masses in place: each row (column) is read and rewritten by the one thread that owns
-    // it, and the barrier between the passes orders the row writes before the column reads
-    if (D == 3) {
-      if (in_block && t1 < k) {
-        T *row = &sa[(f * k + t1) * TL + t2 * K];
-        T r[K];
-#pragma unroll
-        for (int m = 0; m < K; ++m) r[m] = row[m];
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-          T s = T(0);
-#pragma unroll
-          for (int m = 0; m < K; ++m) s = fma(M[q * K + m], r[m], s);
-          row[q] = s;
-        }
-      }
-      __syncthreads();
-      if (in_block && t2 < k) {
-        T *col = &sa[(f * k + t2) * TL + t1];
-        T r[K];
-#pragma unroll
-        for (int m = 0; m < K; ++m) r[m] = col[m * K];
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-          T s = T(0);
-#pragma unroll
-          for (int m = 0; m < K; ++m) s = fma(M[q * K + m], r[m], s);
-          col[q * K] = s;
-        }
-      }
-      __syncthreads();
-    } else {
-      if (in_block && t < k) {
-        T *row = &sa[(f * k + t) * TL];
-        T r[K];
-#pragma unroll
-        for (int m = 0; m < K; ++m) r[m] = row[m];
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-          T s = T(0);
-#pragma unroll
-          for (int m = 0; m < K; ++m) s = fma(M[q * K + m], r[m], s);
-          row[q] = s;
-        }
-      }
-      __syncthreads();
-    }
-    const T *res = sa;
-    T cj[k];
-#pragma unroll
-    for (int j = 0; j < k; ++j) cj[j] = in_block ? res[(f * k + j) * TL + t] : T(0);
-    if (live) {
-      // expansion y_i = sum_j gs_j[i] c_j, folded: E_i from the symmetric orders, O_i from the others
-      T yv[NN];
-#pragma unroll
-      for (int i = 0; i <= k; ++i) {
-        T e = T(0), o = T(0);
 #pragma unroll
         for (int j = 0; j < k; ++j) {
-          if (j % 2 == 0)
-            e = fma(gs[j * NN + i], cj[j], e);
-          else if (i < k)
-            o = fma(gs[j * NN + i], cj[j], o);
+          T s, su = T(0);
+          if (j % 2 == 0) {
+            s = T(Tab::g[j * NN + k]) * line[k];
+            if (VJP) su = T(Tab::g[j * NN + k]) * uline[k];
+#pragma unroll
+            for (int i = 0; i < k; ++i) {
+              s = fma(T(Tab::g[j * NN + i]), ev[i], s);
+              if (VJP) su = fma(T(Tab::g[j * NN + i]), eu[i], su);
+            }
+          } else {
+            s = T(0);
+#pragma unroll
+            for (int i = 0; i < k; ++i) {
+              s = fma(T(Tab::g[j * NN + i]), od[i], s);
+              if (VJP) su = fma(T(Tab::g[j * NN + i]), ou[i], su);
+            }
+          }
+          a[j] = s;
+          au[j] = su;
         }
-        yv[i] = e + o;
-        if (i < k) yv[2 * k - i] = e - o;
       }
-      const int axis = cur.axis, rn = cur.rn, ra = cur.ra, rb = cur.rb;
+      if (in_block) {
 #pragma unroll
-      for (int i = 0; i < NN; ++i) {
-        if (i >= ilo && i <= ihi) {
-          const int xn = rn + i;
-          const int bx0 = axis == 0 ? xn : ra;
-          const int by = axis == 1 ? xn : (axis == 0 ? ra : rb);
-          const int bz = axis == 2 ? xn : rb;
-          __hip_atomic_fetch_add(&acc[box_slot(D, bx0, by, D == 3 ? bz : 0)], yv[i], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (int j = 0; j < k; ++j) sa[(f * k + j) * TL + t] = a[j];
+      }
+      __syncthreads();
+      if (last && accumulate) {  // y at the exclusive flush nodes
+#pragma unroll
+        for (int m = 0; m < kLines; ++m) yv[m] = yb[(uint32_t)(fa[m] >= 0 && fa[m] < (1 << 16) ? fs[m] : 0)];
+      }
+      // issue the next gather: the next batch of this box, or the first batch of the next box
+      if (!last || nxt >= 0) {
+        const int vi = last ? f : (b + 1) * FPB + f;
+        const int nv = last ? bn.visit_count : bc.visit_count;
+        const bool live = in_block && vi < nv;
+        const Visit v = live ? svis[last ? buf ^ 1 : buf][vi] : Visit(0);
+        const int64_t gb = last ? nbase + nglo : box_base + glo;
+        nxp = last ? prep_visit<D, K>(v, live, t1, t2, s1, s2, bn.o0, bn.o1, bn.o2, nglo)
+                   : prep_visit<D, K>(v, live, t1, t2, s1, s2, bc.o0, bc.o1, bc.o2, glo);
+        const T *xg = x + gb;
+        const T *ug = VJP ? u2 + gb : nullptr;
+#pragma unroll
+        for (int i = 0; i < NN; ++i) {
+          lnext[i] = xg[nxp.gofs + i * nxp.sn];
+          if (VJP) unext[i] = ug[nxp.gofs + i * nxp.sn];
         }
       }
-      if (VJP && prim) {
+      // tangential masses in place: each row (column) is read and rewritten by the one thread that owns
+      // it, and the barrier between the passes orders the row writes before the column reads
+      if (D == 3) {
+        if (in_block && t1 < k) {
+          T *row = &sa[(f * k + t1) * TL + t2 * K];
+          T r[K];
 #pragma unroll
-        for (int j = 0; j < k; ++j) pj[j] += (double)au[j] * (double)cj[j];
+          for (int m = 0; m < K; ++m) r[m] = row[m];
+#pragma unroll
+          for (int q = 0; q < K; ++q) {
+            T s = T(0);
+#pragma unroll
+            for (int m = 0; m < K; ++m) s = fma(T(Tab::M[q * K + m]), r[m], s);
+            row[q] = s;
+          }
+        }
+        __syncthreads();
+        if (in_block && t2 < k) {
+          T *col = &sa[(f * k + t2) * TL + t1];
+          T r[K];
+#pragma unroll
+          for (int m = 0; m < K; ++m) r[m] = col[m * K];
+#pragma unroll
+          for (int q = 0; q < K; ++q) {
+            T s = T(0);
+#pragma unroll
+            for (int m = 0; m < K; ++m) s = fma(T(Tab::M[q * K + m]), r[m], s);
+            col[q * K] = s;
+          }
+        }
+        __syncthreads();
+      } else {
+        if (in_block && t < k) {
+          T *row = &sa[(f * k + t) * TL];
+          T r[K];
+#pragma unroll
+          for (int m = 0; m < K; ++m) r[m] = row[m];
+#pragma unroll
+          for (int q = 0; q < K; ++q) {
+            T s = T(0);
+#pragma unroll
+            for (int m = 0; m < K; ++m) s = fma(T(Tab::M[q * K + m]), r[m], s);
+            row[q] = s;
+          }
+        }
+        __syncthreads();
+      }
+      T cj[k];
+#pragma unroll
+      for (int j = 0; j < k; ++j) cj[j] = in_block ? sa[(f * k + j) * TL + t] : T(0);
+      if (cur_p.live) {
+        // expansion y_i = sum_j coef_j g_j[i] c_j (coef_j = gamma_j h^{d-1-2j}), folded: E_i from the
+        // symmetric orders, O_i from the others, y_i = E_i + O_i and y_{2k-i} = E_i - O_i
+        T cs[k];
+#pragma unroll
+        for (int j = 0; j < k; ++j) cs[j] = coef[j] * cj[j];
+        T yv2[NN];
+#pragma unroll
+        for (int i = 0; i <= k; ++i) {
+          T e = T(0), o = T(0);
+#pragma unroll
+          for (int j = 0; j < k; ++j) {
+            if (j % 2 == 0)
+              e = fma(T(Tab::g[j * NN + i]), cs[j], e);
+            else if (i < k)
+              o = fma(T(Tab::g[j * NN + i]), cs[j], o);
+          }
+          yv2[i] = e + o;
+          if (i < k) yv2[2 * k - i] = e - o;
+        }
+        if (cur_p.lo) {
+          int off = cur_p.acc0;
+#pragma unroll
+          for (int i = 0; i <= k; ++i, off += cur_p.dacc)
+            __hip_atomic_fetch_add(reinterpret_cast<A *>(accb + off), (A)yv2[i], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if (cur_p.hi) {
+          int off = cur_p.acc0 + (k + 1) * cur_p.dacc;
+#pragma unroll
+          for (int i = k + 1; i < NN; ++i, off += cur_p.dacc)
+            __hip_atomic_fetch_add(reinterpret_cast<A *>(accb + off), (A)yv2[i], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if (VJP && cur_p.prim) {
+#pragma unroll
+          for (int j = 0; j < k; ++j) pj[j] += (double)au[j] * (double)cj[j];
+        }
+      }
+      __syncthreads();  // sa is reused by the next batch, acc is complete after the last
+    }
+
+    // flush: exclusive nodes to y, shared ones to their halo slot
+#pragma unroll
+    for (int m = 0; m < kLines; ++m) {
+      if (fa[m] >= 0) {
+        A v = *reinterpret_cast<const A *>(accb + (fa[m] & 0xFFFF));
+        if (fa[m] >> 16) {
+          halo[fs[m]] = (T)v;
+        } else {
+          if (accumulate) v += (A)yv[m];
+          yb[(uint32_t)fs[m]] = (T)v;
+        }
       }
     }
-    __syncthreads();  // sa / sb are reused by the next batch, acc is complete after the last
-  }
-  }
-
-  // flush: exclusive nodes to y, shared ones to their halo slot (no global loads here)
+    if (VJP) {
+      __shared__ double red[kBoxThreads / 64][k];
+      const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-  for (int m = 0; m < kLines; ++m) {
-    if (fa[m] >= 0) {
-      const T v = acc[fa[m] & 0xFFF];
-      if (fa[m] >> 12)
-        halo[fs[m]] = v;
-      else
-        y[box_base + fs[m]] = v;
+      for (int j = 0; j < k; ++j) {
+        double v = pj[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[wave][j] = v;
+      }
+      __syncthreads();
+      if (tid < k) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBoxThreads / 64; ++w) sum += red[w][tid];
+        partial[(int64_t)cur * k + tid] = sum;
+      }
     }
-  }
-
-  if (VJP) {
-    __shared__ double red[kBoxThreads / 64][k];
-    const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int j = 0; j < k; ++j) {
-      double v = pj[j];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-      if (lane == 0) red[wave][j] = v;
-    }
-    __syncthreads();
-    if (tid < k) {
-      double s = 0.0;
-#pragma unroll
-      for (int w = 0; w < kBoxThreads / 64; ++w) s += red[w][tid];
-      partial[(int64_t)bi * k + tid] = s;
-    }
+    if (tid == 0) s_box[0] = after;
+    __syncthreads();  // acc read by the flush before the next zeroing; s_box published
+    if (nxt < 0) break;
+    cur = nxt;
+    bc = bn;
+    box_base = nbase;
+    glo = nglo;
+    nxt = __builtin_amdgcn_readfirstlane(s_box[0]);
+    buf ^= 1;
   }
 }
 
 #define GHOST_BOX_PARAMS                                                                                  \
   const T *__restrict__ x, const T *__restrict__ u2, T *__restrict__ y, T *__restrict__ halo,             \
       double *__restrict__ partial, const Box *__restrict__ boxes, const Visit *__restrict__ visits,      \
-      const BoxLine *__restrict__ lines, const T *__restrict__ tab, int s0, int s1, int s2, int accumulate
-#define GHOST_BOX_ARGS x, u2, y, halo, partial, boxes, visits, lines, tab, s0, s1, s2, accumulate
+      const BoxLine *__restrict__ lines, const T *__restrict__ tab, int s1, int s2, int accumulate,     \
+      int n_boxes, BoxSched *__restrict__ sched
+#define GHOST_BOX_ARGS x, u2, y, halo, partial, boxes, visits, lines, tab, s1, s2, accumulate, n_boxes, sched
 
 // Two blocks of 512 threads per CU need at most 128 VGPRs (4 waves per SIMD); the compiler is held to
 // that where it fits without spilling (the apply up to k = 6).  The VJP and k = 7 carry more live
@@ -589,17 +710,32 @@ __global__ void vjp_reduce_kernel(const double *__restrict__ partial, int n_batc
   if (tid == 0) dgamma[j] = hscale[j] * red[0];
 }
 
-// gs_j = gamma_j * hscale_j * g_j in FP64, and its FP32 rounding.
-__global__ void set_gamma_kernel(const double *__restrict__ gamma, int k, double *__restrict__ tab64,
-                                 float *__restrict__ tab32) {
+// gs_j = gamma_j * hscale_j * g_j and coef_j = gamma_j * hscale_j in FP64, and their FP32 roundings.
+__device__ void write_gamma_tables(const double *gamma, int k, double *__restrict__ tab64,
+                                   float *__restrict__ tab32) {
   const int NN = 2 * k + 1;
-  const double *hscale = tab64 + 2 * k * NN + (k + 1) * (k + 1);
+  const double *hscale = tab64 + tab_hscale(k);
   for (int idx = threadIdx.x; idx < k * NN; idx += blockDim.x) {
     const int j = idx / NN;
     const double v = (gamma[j] * hscale[j]) * tab64[idx];
     tab64[k * NN + idx] = v;
     tab32[k * NN + idx] = (float)v;
   }
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    const double c = gamma[j] * hscale[j];
+    tab64[tab_coef(k) + j] = c;
+    tab32[tab_coef(k) + j] = (float)c;
+  }
+}
+
+__global__ void set_gamma_kernel(const double *__restrict__ gamma, int k, double *__restrict__ tab64,
+                                 float *__restrict__ tab32) {
+  write_gamma_tables(gamma, k, tab64, tab32);
+}
+
+// Same, with gamma passed by value from the host.
+__global__ void set_gamma_host_kernel(GammaArg g, int k, double *__restrict__ tab64, float *__restrict__ tab32) {
+  write_gamma_tables(g.v, k, tab64, tab32);
 }
 
 __global__ void fill_kernel(double *__restrict__ y, int64_t n, double v) {
@@ -673,13 +809,26 @@ hipError_t dispatch(const DevPlan &p, const T *x, const T *u2, T *y, double *par
 template <typename T, int D, int K, bool VJP>
 void launch_box(const DevPlan &p, const T *x, const T *u2, T *y, T *halo, const T *tab, bool accumulate,
                 hipStream_t s) {
-  const dim3 grid(p.n_boxes), block(kBoxThreads);
-  if constexpr (VJP || K == 8)
+  // persistent workgroups: as many as fit on the device at once (the first launch asks the runtime)
+  const void *fn;
+  if constexpr (VJP)
+    fn = reinterpret_cast<const void *>(&box_kernel_wide<T, D, K, VJP>);
+  else
+    fn = reinterpret_cast<const void *>(&box_kernel<T, D, K, VJP>);
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBoxThreads, 0) != hipSuccess || nb < 1) nb = 1;
+    per_cu = nb;
+  }
+  const int resident = per_cu * (p.n_cu > 0 ? p.n_cu : 1);
+  const dim3 grid(p.n_boxes < resident ? p.n_boxes : resident), block(kBoxThreads);
+  if constexpr (VJP)
     hipLaunchKernelGGL((box_kernel_wide<T, D, K, VJP>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes,
-                       p.visits, p.box_lines, tab, p.stride[0], p.stride[1], p.stride[2], (int)accumulate);
+                       p.visits, p.box_lines, tab, p.stride[1], p.stride[2], (int)accumulate, p.n_boxes, p.sched);
   else
     hipLaunchKernelGGL((box_kernel<T, D, K, VJP>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes,
-                       p.visits, p.box_lines, tab, p.stride[0], p.stride[1], p.stride[2], (int)accumulate);
+                       p.visits, p.box_lines, tab, p.stride[1], p.stride[2], (int)accumulate, p.n_boxes, p.sched);
 }
 
 template <typename T, bool VJP>
@@ -767,6 +916,11 @@ hipError_t launch_vjp(const DevPlan &p, const double *u, const double *w, double
 
 hipError_t launch_set_gamma(const DevPlan &p, const double *gamma_dev, hipStream_t s) {
   hipLaunchKernelGGL(set_gamma_kernel, dim3(1), dim3(128), 0, s, gamma_dev, p.k, p.tab64, p.tab32);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_gamma_host(const DevPlan &p, GammaArg g, hipStream_t s) {
+  hipLaunchKernelGGL(set_gamma_host_kernel, dim3(1), dim3(128), 0, s, g, p.k, p.tab64, p.tab32);
   return hipGetLastError();
 }
 

@@ -444,7 +444,7 @@ std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], dou
 
 std::string build_box_layout(Plan &p) {
   const int d = p.dim, k = p.k;
-  const int B = box_cells(d, k), NB = box_nodes(d, k), E = box_extent(d);
+  const int B = box_cells(d, k), NB = box_nodes(d, k), E = box_extent(d), P = box_pitch(d);
   const int64_t kB = (int64_t)k * B;
   int nbr[3] = {1, 1, 1};
   for (int a = 0; a < d; ++a) nbr[a] = (p.n[a] + B - 1) / B;
@@ -488,74 +488,109 @@ std::string build_box_layout(Plan &p) {
   p.box_runs.clear();
   p.box_lines.clear();
   if (NB > E) return "box node extent exceeds the accumulator extent";
-  struct HaloRef { int64_t node; int32_t slot; };
-  std::vector<HaloRef> halo;
-  int64_t slots = 0;
+  {
+    // the kernel addresses u and y around a box with 32-bit byte offsets: nodes within E + k of the
+    // box origin along each axis (k below it for the lower cells of split faces)
+    const int64_t s1 = p.L[0], s2 = d == 3 ? p.L[0] * p.L[1] : 0;
+    if ((int64_t)8 * (E + 2 * k) * (1 + s1 + s2) >= ((int64_t)1 << 31))
+      return "lattice planes too large for the box scatter (use the atomic scatter)";
+  }
+  // Boxes: one per brick with visits, in brick order; a brick with more visits than one box holds is
+  // split into several boxes over the same node box.  Within a box the visits are interleaved so that
+  // the faces of one batch (consecutive visits) come from different parts of the brick and rarely add
+  // into the same accumulator nodes.
+  struct BoxTmp {
+    int64_t brick;
+    std::vector<Visit> v;
+    std::vector<Run> runs;  // nodes the box contributes to
+  };
+  std::vector<BoxTmp> tmp;
   for (const auto &o : order) {
-    const int64_t b = o.second;
-    const int bb[3] = {(int)(b % nbr[0]), (int)((b / nbr[0]) % nbr[1]), (int)(b / ((int64_t)nbr[0] * nbr[1]))};
-    Box bx{};
-    bool sh_lo[3] = {false, false, false}, sh_hi[3] = {false, false, false};
-    for (int a = 0; a < 3; ++a) {
-      bx.org[a] = a < d ? (int32_t)(kB * bb[a]) : 0;
-      if (a < d) {
-        sh_lo[a] = bb[a] > 0;
-        sh_hi[a] = (int64_t)B * (bb[a] + 1) < p.n[a];
-      }
+    const std::vector<Visit> &all = bv[o.second];
+    const size_t nparts = (all.size() + kMaxBoxVisits - 1) / kMaxBoxVisits;
+    for (size_t part = 0; part < nparts; ++part) {
+      BoxTmp t;
+      t.brick = o.second;
+      for (size_t i = part; i < all.size(); i += nparts) t.v.push_back(all[i]);
+      tmp.push_back(std::move(t));
     }
-    bx.visit_first = (int32_t)p.visits.size();
-    bx.visit_count = (int32_t)bv[b].size();
-    {
-      // Interleave the brick's visits so that the faces of one batch (consecutive visits) come from
-      // different parts of the brick and rarely add into the same accumulator nodes.
-      const size_t nv = bv[b].size(), fpb = (size_t)faces_per_block(d, k);
-      const size_t nbatch = (nv + fpb - 1) / fpb;
-      for (size_t q = 0; q < nbatch; ++q)
-        for (size_t r = 0; r < fpb; ++r)
-          if (q + r * nbatch < nv) p.visits.push_back(bv[b][q + r * nbatch]);
+  }
+  // Touched nodes of each box (union over its visits of the expanded part of the patch), and how
+  // many boxes touch each support node: a node touched by one box is written by that box, the
+  // others go through halo slots.
+  std::vector<int64_t> sup_start(p.support_runs.size()), sup_off(p.support_runs.size());
+  {
+    int64_t acc = 0;
+    for (size_t r = 0; r < p.support_runs.size(); ++r) {
+      sup_start[r] = p.support_runs[r].start;
+      sup_off[r] = acc;
+      acc += p.support_runs[r].len;
     }
-
-    // nodes this brick contributes to: union over its visits of the expanded part of the patch
+  }
+  auto sup_index = [&](int64_t node) -> int64_t {
+    const size_t r = (size_t)(std::upper_bound(sup_start.begin(), sup_start.end(), node) - sup_start.begin()) - 1;
+    return sup_off[r] + (node - sup_start[r]);
+  };
+  std::vector<uint8_t> touches((size_t)p.n_support, 0);
+  for (BoxTmp &t : tmp) {
     std::vector<Interval> iv;
-    for (Visit v : bv[b]) {
+    for (Visit v : t.v) {
       const int c[3] = {(int)(v & 0xFFFFF), (int)((v >> 20) & 0xFFFFF), (int)((v >> 40) & 0xFFFFF)};
       const int a = (int)((v >> 60) & 3), half = (int)((v >> 62) & 3);
       int64_t lo[3], hi[3];  // node ranges, inclusive
-      for (int t = 0; t < 3; ++t) {
-        lo[t] = t < d ? (int64_t)k * c[t] : 0;
-        hi[t] = t < d ? lo[t] + k : 0;
+      for (int q = 0; q < 3; ++q) {
+        lo[q] = q < d ? (int64_t)k * c[q] : 0;
+        hi[q] = q < d ? lo[q] + k : 0;
       }
       if (half == 0) hi[a] = lo[a] + 2 * k;
       if (half == 2) { lo[a] = (int64_t)k * c[a] + k + 1; hi[a] = (int64_t)k * c[a] + 2 * k; }
       for (int64_t z = lo[2]; z <= hi[2]; ++z)
         for (int64_t y = lo[1]; y <= hi[1]; ++y) iv.push_back({y + p.L[1] * z, lo[0], hi[0] + 1});
     }
-    std::vector<Run> runs;
     int64_t tot = 0;
-    merge_runs(iv, p.L[0], runs, tot);
+    merge_runs(iv, p.L[0], t.runs, tot);
+    for (const Run &r : t.runs) {
+      const int64_t base = sup_index(r.start);
+      for (int64_t q = 0; q < r.len; ++q)
+        if (touches[base + q] < 255) ++touches[base + q];
+    }
+  }
+
+  struct HaloRef { int64_t node; int32_t slot; };
+  std::vector<HaloRef> halo;
+  int64_t slots = 0;
+  const size_t fpb = (size_t)box_faces_per_batch(d, k);
+  for (const BoxTmp &t : tmp) {
+    const int64_t b = t.brick;
+    const int bb[3] = {(int)(b % nbr[0]), (int)((b / nbr[0]) % nbr[1]), (int)(b / ((int64_t)nbr[0] * nbr[1]))};
+    Box bx{};
+    for (int a = 0; a < 3; ++a) bx.org[a] = a < d ? (int32_t)(kB * bb[a]) : 0;
+    bx.visit_first = (int32_t)p.visits.size();
+    bx.visit_count = (int32_t)t.v.size();
+    {
+      const size_t nv = t.v.size(), nbatch = (nv + fpb - 1) / fpb;
+      for (size_t q = 0; q < nbatch; ++q)
+        for (size_t r = 0; r < fpb; ++r)
+          if (q + r * nbatch < nv) p.visits.push_back(t.v[q + r * nbatch]);
+    }
     bx.run_first = (int32_t)p.box_runs.size();
     bx.line_first = (int32_t)p.box_lines.size();
-    for (const Run &r : runs) {
+    for (const Run &r : t.runs) {
       const int64_t line = r.start / p.L[0], x0 = r.start % p.L[0];
       const int64_t Y = line % p.L[1], Z = line / p.L[1];
       const int64_t ry = d >= 2 ? Y - bx.org[1] : 0, rz = d >= 3 ? Z - bx.org[2] : 0;
-      const bool line_shared = (d >= 2 && ((ry == 0 && sh_lo[1]) || (ry == kB && sh_hi[1]))) ||
-                               (d >= 3 && ((rz == 0 && sh_lo[2]) || (rz == kB && sh_hi[2])));
-      // split the run at shared x-planes
-      int64_t x = x0;
-      const int64_t xe = x0 + r.len;
-      while (x < xe) {
-        const int64_t rx = x - bx.org[0];
-        const bool node_shared = line_shared || (rx == 0 && sh_lo[0]) || (rx == kB && sh_hi[0]);
-        int64_t e = x + 1;
-        if (!line_shared && !node_shared)
-          while (e < xe && !((e - bx.org[0] == kB) && sh_hi[0])) ++e;
-        else if (line_shared)
-          e = xe;
+      const int64_t sbase = sup_index(r.start);
+      // split the run where the shared status changes
+      int64_t q0 = 0;
+      while (q0 < r.len) {
+        const bool node_shared = touches[sbase + q0] > 1;
+        int64_t q1 = q0 + 1;
+        while (q1 < r.len && (touches[sbase + q1] > 1) == node_shared) ++q1;
+        const int64_t rx = x0 + q0 - bx.org[0];
         BoxRun br{};
-        br.start = x + p.L[0] * line;
-        br.acc = (int32_t)(rx + E * (ry + (int64_t)E * rz));  // box-linear index (before the slot rotation)
-        br.len = (int32_t)(e - x);
+        br.start = r.start + q0;
+        br.acc = (int32_t)(rx + P * (ry + (int64_t)E * rz));  // accumulator index
+        br.len = (int32_t)(q1 - q0);
         br.slot = -1;
         if (node_shared) {
           br.slot = (int32_t)slots;
@@ -572,15 +607,17 @@ std::string build_box_layout(Plan &p) {
           bl.touched |= (uint64_t)1 << (rx + q);
           if (node_shared) bl.shared |= (uint64_t)1 << (rx + q);
         }
-        x = e;
+        q0 = q1;
       }
     }
     bx.run_count = (int32_t)(p.box_runs.size() - bx.run_first);
     bx.line_count = (int32_t)(p.box_lines.size() - bx.line_first);
-    // the kernel reads the first visit and line of every box unconditionally, and one lane group per
-    // box line: a box has at least one of each and at most one line per (y, z) of its node box
-    if (bx.visit_count < 1 || bx.line_count < 1 || bx.line_count > (d == 3 ? E * E : E))
-      return "box layout: a box without visits or lines, or with more lines than its node box";
+    // the kernel reads the first visit and line of every box unconditionally, one visit per thread
+    // and one lane group per box line: a box has at least one of each, at most kMaxBoxVisits visits
+    // and at most one line per (y, z) of its node box
+    if (bx.visit_count < 1 || bx.visit_count > kMaxBoxVisits || bx.line_count < 1 ||
+        bx.line_count > (d == 3 ? E * E : E))
+      return "box layout: a box without visits or lines, or with more visits or lines than it holds";
     p.boxes.push_back(bx);
   }
   if (slots >= ((int64_t)1 << 31) || (int64_t)p.visits.size() >= ((int64_t)1 << 31))

@@ -72,6 +72,25 @@ def test_tables_reflection_symmetry_exact(k):
         np.testing.assert_allclose(v[::-1], (-1) ** (m + 1) * v, rtol=0, atol=1e-13 * np.abs(v).max())
 
 
+def test_generated_tables_match_runtime_tables():
+    """The kernels' compile-time jump vectors and mass matrices (written at build time) are bit-identical
+    to the tables the library builds at run time (and which the oracle comparison above pins)."""
+    path = os.path.join(ROOT, "_build", "ghost_tables_gen.h")
+    text = open(path).read()
+    blocks = re.findall(r"struct Tab1d<(\d+)> \{\s*static constexpr double g\[\d+\] = \{([^}]*)\};\s*"
+                        r"static constexpr double M\[\d+\] = \{([^}]*)\};", text)
+    assert [int(b[0]) for b in blocks] == list(range(2, 9))
+    w = WORKLOADS["disk2d_q2_32"]
+    for K, g, M in blocks:
+        k = int(K) - 1
+        op = GhostOperator(2, w.n, w.lo, w.h, k, gamma_paper(k, w.h), centre=w.centre, radius=w.radius, device=-1)
+        t = op.tables()
+        gv = np.array([float.fromhex(x.strip()) for x in g.split(",")])
+        Mv = np.array([float.fromhex(x.strip()) for x in M.split(",")])
+        assert np.array_equal(gv, np.asarray(t["jumps"]).ravel())
+        assert np.array_equal(Mv, np.asarray(t["mass"]).ravel())
+
+
 @pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64"])
 def test_plan_matches_oracle(name):
     w = WORKLOADS[name]
@@ -203,15 +222,18 @@ def test_host_only_context_refuses_device_work(lib):
     lib.ghost_destroy(None)  # no-op
 
 
-@pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64", "small3d_q5_24", "small3d_q7_14"])
+@pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64", "small3d_q5_24", "small3d_q7_14", "small3d_q2_24",
+                                  "small3d_q1_20"])
 def test_box_layout(name):
     """Box scatter layout: runs of all boxes cover the support exactly; a node is either exclusive to one
     box (written to y) or routed through halo slots by every box touching it; each face is visited once
     (whole patch) or twice (lower / upper cell, by the bricks of those cells); run accumulator indices
-    are the box-relative node coordinates, x + E*(y + E*z) with E the accumulator extent."""
+    are the box-relative node coordinates, x + P*(y + E*z) with E the accumulator extent, P = E + 1."""
     from paper_2503_00246_amd.workloads import Workload
     extra = {"small3d_q5_24": Workload("s", 3, 5, (24,) * 3, (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73),
-             "small3d_q7_14": Workload("s", 3, 7, (14, 13, 12), (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)}
+             "small3d_q7_14": Workload("s", 3, 7, (14, 13, 12), (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73),
+             "small3d_q2_24": Workload("s", 3, 2, (24,) * 3, (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73),
+             "small3d_q1_20": Workload("s", 3, 1, (20, 19, 18), (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)}
     w = WORKLOADS.get(name) or extra[name]
     op = _host(w)
     boxes, visits, runs = op.box_layout()
@@ -219,6 +241,7 @@ def test_box_layout(name):
     B = 15 // k if d == 3 else 63 // k
     NB = k * B + 1
     E = 16 if d == 3 else 64
+    P = E + 1
     assert NB <= E
     assert op.stats["brick"] == B
     L_ = np.array(list(w.lattice) + [1] * (3 - d))
@@ -236,6 +259,12 @@ def test_box_layout(name):
     excl_nodes = nodes[~shared]
     assert len(np.unique(excl_nodes)) == len(excl_nodes)
     assert len(np.intersect1d(excl_nodes, nodes[shared])) == 0
+    # a node is shared exactly when more than one box touches it (a box touches a node at most once)
+    assert len(np.unique(np.stack([nodes, rbox]), axis=1)[0]) == len(nodes)
+    uq, inv, cnt = np.unique(nodes, return_inverse=True, return_counts=True)
+    assert np.array_equal(shared, cnt[inv] > 1)
+    # at most one visit per thread of the box kernel
+    assert boxes[:, 4].max() <= 512 and boxes[:, 4].min() >= 1
     assert op.stats["n_halo_slots"] == int(shared.sum())
     assert op.stats["n_halo_nodes"] == len(np.unique(nodes[shared]))
     slots = np.concatenate([np.arange(sl, sl + n_) for _, _, n_, sl in runs if sl >= 0] + [np.zeros(0, np.int64)])
@@ -245,7 +274,7 @@ def test_box_layout(name):
     rel = I - boxes[rbox, 0:3]
     assert np.all(rel >= 0) and np.all(rel[:, :d] < NB)
     accs = np.concatenate([np.arange(a_, a_ + n_) for _, a_, n_, _ in runs])
-    assert np.array_equal(accs, rel[:, 0] + E * (rel[:, 1] + E * rel[:, 2]))
+    assert np.array_equal(accs, rel[:, 0] + P * (rel[:, 1] + E * rel[:, 2]))
     # visits
     v = visits.astype(np.uint64)
     c = np.stack([(v & 0xFFFFF), (v >> 20) & 0xFFFFF, (v >> 40) & 0xFFFFF], -1).astype(np.int64)
