@@ -186,8 +186,9 @@ typedef struct {
 
 /*
  * Solve (M + G) x = b from x = 0.  b, x: DEVICE arrays of n_lattice doubles; b must be
- * zero on inactive nodes (x is written there as zero).  Synchronous: returns when the
- * solve ends.  Allocates its workspace on the first call (kept until ghost_destroy).
+ * zero on inactive nodes.  x is written on the active nodes only; its other entries are
+ * left as they were.  Synchronous: returns when the solve ends.  Allocates its workspace
+ * on the first call (kept until ghost_destroy).
  */
 int ghost_cg(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts *opts,
              ghost_cg_result *res, void *stream);
@@ -224,6 +225,19 @@ int ghost_tables(const ghost_ctx *ctx, double *jumps, double *mass, double *node
  */
 int ghost_box_layout(const ghost_ctx *ctx, int32_t *boxes, int64_t box_cap, uint64_t *visits,
                      int64_t visit_cap, int64_t *runs, int64_t run_cap);
+
+/*
+ * Per-kernel timing (a profiling aid).  ghost_set_timing(ctx, 1) makes every later apply, FP32
+ * apply and VJP on the context record HIP events on its stream around its scatter kernel
+ * (the box kernel, or all face kernels) and around the halo pass that follows it;
+ * ghost_set_timing(ctx, 0) stops recording.  ghost_kernel_times waits for the recorded
+ * events, returns the summed durations in milliseconds (main_ms: scatter kernels, halo_ms:
+ * halo pass) and the number of recorded calls in *calls, and starts a new sum.  Event
+ * records are not meant for streams under graph capture.  Host pointers; NULL outputs are
+ * skipped.  GHOST_ESTATE on a host-only context.
+ */
+int ghost_set_timing(ghost_ctx *ctx, int on);
+int ghost_kernel_times(ghost_ctx *ctx, double *main_ms, double *halo_ms, int64_t *calls);
 
 /* Release the context and every allocation it owns.  NULL is a no-op. */
 void ghost_destroy(ghost_ctx *ctx);

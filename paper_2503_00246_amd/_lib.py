@@ -17,7 +17,7 @@ GHOST_CG_FP64, GHOST_CG_MIXED = 0, 1
 
 EXPORTS = ["ghost_setup", "ghost_set_gamma", "ghost_apply", "ghost_apply_f32", "ghost_vjp",
            "ghost_mass_diag", "ghost_cg", "ghost_info", "ghost_faces", "ghost_tables", "ghost_box_layout",
-           "ghost_destroy", "ghost_last_error"]
+           "ghost_destroy", "ghost_last_error", "ghost_set_timing", "ghost_kernel_times"]
 
 
 class GhostMesh(ctypes.Structure):
@@ -92,6 +92,9 @@ def load(path=LIB_PATH):
     lib.ghost_tables.argtypes = [P] + [ctypes.POINTER(ctypes.c_double)] * 4
     lib.ghost_box_layout.argtypes = [P, ctypes.POINTER(ctypes.c_int32), c_i64, ctypes.POINTER(ctypes.c_uint64),
                                      c_i64, ctypes.POINTER(ctypes.c_int64), c_i64]
+    lib.ghost_set_timing.argtypes = [P, c_int]
+    lib.ghost_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(c_i64)]
     lib.ghost_destroy.argtypes = [P]
     lib.ghost_destroy.restype = None
     lib.ghost_last_error.restype = ctypes.c_char_p

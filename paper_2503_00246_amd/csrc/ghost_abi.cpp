@@ -2,6 +2,7 @@
 // No C++ exception crosses this file's extern "C" functions.
 #include <hip/hip_runtime_api.h>
 
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -23,6 +24,10 @@ struct ghost_ctx {
   std::vector<double> gamma;
   std::vector<void *> allocs;         // device allocations owned by the context
   ghost::CgWork *cg = nullptr;        // lazily allocated CG workspace
+  // per-kernel timing: event triples of the recorded calls since the last read (pool reused)
+  bool timing = false;
+  std::vector<std::array<hipEvent_t, 3>> events;
+  size_t events_used = 0;
 };
 
 namespace {
@@ -84,6 +89,10 @@ int upload(ghost_ctx *c, const T *src, size_t n, T **dst) {
 void free_device(ghost_ctx *c) {
   if (c->device < 0) return;
   DeviceGuard g(c->device);
+  for (auto &t : c->events)
+    for (hipEvent_t e : t)
+      if (e) (void)hipEventDestroy(e);
+  c->events.clear();
   if (c->cg) ghost::cg_free(c->cg);
   c->cg = nullptr;
   for (void *p : c->allocs) (void)hipFree(p);
@@ -201,7 +210,7 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
   }
   d.n_batches = (int)p.batches.size();
   d.scatter = (flags & GHOST_COLOURED) ? ghost::Scatter::Coloured
-              : (flags & GHOST_ATOMIC) ? ghost::Scatter::Atomic : ghost::Scatter::Owner;
+              : (flags & GHOST_ATOMIC) ? ghost::Scatter::Atomic : ghost::Scatter::Box;
   d.n_boxes = (int)p.boxes.size();
   d.n_halo = (int)p.halo_node.size();
   d.coloured = p.coloured;
@@ -309,12 +318,31 @@ int ghost_set_gamma(ghost_ctx *ctx, const double *gamma, int gamma_on_device, vo
   return e == hipSuccess ? GHOST_OK : fail_hip(e, "set_gamma launch");
 }
 
+// The device plan of a launch: with timing on, a copy carrying the next event triple of the pool.
+int launch_plan(ghost_ctx *ctx, ghost::DevPlan &out) {
+  out = ctx->dev;
+  if (!ctx->timing) return GHOST_OK;
+  if (ctx->events_used == ctx->events.size()) {
+    std::array<hipEvent_t, 3> t{};
+    for (auto &e : t) {
+      const hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return fail_hip(r, "hipEventCreate");
+    }
+    ctx->events.push_back(t);
+  }
+  const auto &t = ctx->events[ctx->events_used++];
+  for (int i = 0; i < 3; ++i) out.ev[i] = t[i];
+  return GHOST_OK;
+}
+
 int ghost_apply(ghost_ctx *ctx, const double *u, double *y, int accumulate, void *stream) {
   int rc = check_apply(ctx, u, y, sizeof(double));
   if (rc) return rc;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail_hip(g.err, "hipSetDevice");
-  hipError_t e = ghost::launch_apply_f64(ctx->dev, u, y, accumulate != 0, static_cast<hipStream_t>(stream));
+  ghost::DevPlan dp;
+  if ((rc = launch_plan(ctx, dp))) return rc;
+  hipError_t e = ghost::launch_apply_f64(dp, u, y, accumulate != 0, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? GHOST_OK : fail_hip(e, "apply launch");
 }
 
@@ -323,7 +351,9 @@ int ghost_apply_f32(ghost_ctx *ctx, const float *u, float *y, int accumulate, vo
   if (rc) return rc;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail_hip(g.err, "hipSetDevice");
-  hipError_t e = ghost::launch_apply_f32(ctx->dev, u, y, accumulate != 0, static_cast<hipStream_t>(stream));
+  ghost::DevPlan dp;
+  if ((rc = launch_plan(ctx, dp))) return rc;
+  hipError_t e = ghost::launch_apply_f32(dp, u, y, accumulate != 0, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? GHOST_OK : fail_hip(e, "apply_f32 launch");
 }
 
@@ -336,8 +366,41 @@ int ghost_vjp(ghost_ctx *ctx, const double *u, const double *w, double *du, doub
   if (!dgamma) return fail(GHOST_EINVAL, "null dgamma");
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail_hip(g.err, "hipSetDevice");
-  hipError_t e = ghost::launch_vjp(ctx->dev, u, w, du, dgamma, accumulate_du != 0, static_cast<hipStream_t>(stream));
+  ghost::DevPlan dp;
+  if ((rc = launch_plan(ctx, dp))) return rc;
+  hipError_t e = ghost::launch_vjp(dp, u, w, du, dgamma, accumulate_du != 0, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? GHOST_OK : fail_hip(e, "vjp launch");
+}
+
+int ghost_set_timing(ghost_ctx *ctx, int on) {
+  if (!ctx) return fail(GHOST_EINVAL, "null context");
+  if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");
+  ctx->timing = on != 0;
+  return GHOST_OK;
+}
+
+int ghost_kernel_times(ghost_ctx *ctx, double *main_ms, double *halo_ms, int64_t *calls) {
+  if (!ctx) return fail(GHOST_EINVAL, "null context");
+  if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  double a = 0, b = 0;
+  const size_t n = ctx->events_used;
+  ctx->events_used = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const auto &t = ctx->events[i];
+    float m01 = 0, m12 = 0;
+    hipError_t e = hipEventSynchronize(t[2]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&m01, t[0], t[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&m12, t[1], t[2]);
+    if (e != hipSuccess) return fail_hip(e, "timing events");
+    a += m01;
+    b += m12;
+  }
+  if (main_ms) *main_ms = a;
+  if (halo_ms) *halo_ms = b;
+  if (calls) *calls = (int64_t)n;
+  return GHOST_OK;
 }
 
 int ghost_mass_diag(ghost_ctx *ctx, double *diag, void *stream) {

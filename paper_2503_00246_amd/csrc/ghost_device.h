@@ -23,7 +23,7 @@ __host__ __device__ constexpr int tab_gllw(int k) { return tab_hscale(k) + k; }
 __host__ __device__ constexpr int tab_size64(int k) { return tab_gllw(k) + k + 1; }
 __host__ __device__ constexpr int tab_size32(int k) { return tab_hscale(k); }
 
-enum class Scatter { Owner = 0, Atomic = 1, Coloured = 2 };
+enum class Scatter { Box = 0, Atomic = 1, Coloured = 2 };
 
 // Ticket counters of the persistent box kernel, one pair per scheduling group; zero between launches.
 constexpr int kSchedGroups = 8;
@@ -34,7 +34,7 @@ struct BoxSched {
 
 struct DevPlan {
   int dim = 0, k = 0;
-  Scatter scatter = Scatter::Owner;
+  Scatter scatter = Scatter::Box;
   int32_t stride[3] = {1, 1, 1};
   int n[3] = {1, 1, 1};
   int64_t L[3] = {1, 1, 1};
@@ -65,6 +65,9 @@ struct DevPlan {
   int n_halo = 0;
   BoxSched *sched = nullptr;          // zero-initialised at setup
   int n_cu = 0;                       // compute units of the device
+  // optional timing events: recorded before the scatter kernels, between them and the halo pass,
+  // and after it (all null: no records)
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 
   double *tab64 = nullptr;
   float *tab32 = nullptr;

@@ -831,10 +831,20 @@ void launch_box(const DevPlan &p, const T *x, const T *u2, T *y, T *halo, const 
                        p.visits, p.box_lines, tab, p.stride[1], p.stride[2], (int)accumulate, p.n_boxes, p.sched);
 }
 
+// Optional timing events of a launch (see DevPlan::ev).
+void mark(const DevPlan &p, int i, hipStream_t s) {
+  if (p.ev[i]) (void)hipEventRecord(p.ev[i], s);
+}
+
 template <typename T, bool VJP>
 hipError_t dispatch_box(const DevPlan &p, const T *x, const T *u2, T *y, const T *tab, bool accumulate,
                         hipStream_t s) {
-  if (p.n_boxes <= 0) return hipSuccess;
+  mark(p, 0, s);
+  if (p.n_boxes <= 0) {
+    mark(p, 1, s);
+    mark(p, 2, s);
+    return hipSuccess;
+  }
   T *halo = reinterpret_cast<T *>(p.halo);
   hipError_t e = hipErrorInvalidValue;
 #define GHOST_BCASE(D_, K_)                                           \
@@ -846,11 +856,17 @@ hipError_t dispatch_box(const DevPlan &p, const T *x, const T *u2, T *y, const T
   GHOST_BCASE(2, 8) GHOST_BCASE(3, 2) GHOST_BCASE(3, 3) GHOST_BCASE(3, 4) GHOST_BCASE(3, 5) GHOST_BCASE(3, 6)
   GHOST_BCASE(3, 7) GHOST_BCASE(3, 8)
 #undef GHOST_BCASE
-  if (e != hipSuccess || p.n_halo == 0) return e;
-  hipLaunchKernelGGL((halo_kernel<T>), dim3((p.n_halo + kBlockThreads - 1) / kBlockThreads), dim3(kBlockThreads), 0,
-                     s, y, (const T *)halo, p.halo_node, p.halo_ptr, p.halo_slot, p.n_halo, (int)accumulate);
-  return hipGetLastError();
+  mark(p, 1, s);
+  if (e != hipSuccess) return e;
+  if (p.n_halo > 0) {
+    hipLaunchKernelGGL((halo_kernel<T>), dim3((p.n_halo + kBlockThreads - 1) / kBlockThreads), dim3(kBlockThreads),
+                       0, s, y, (const T *)halo, p.halo_node, p.halo_ptr, p.halo_slot, p.n_halo, (int)accumulate);
+    e = hipGetLastError();
+  }
+  mark(p, 2, s);
+  return e;
 }
+
 
 template <typename T>
 hipError_t zero_support(const DevPlan &p, T *y, hipStream_t s) {
@@ -873,36 +889,46 @@ hipError_t run_faces(const DevPlan &p, const T *x, const T *u2, T *y, const T *t
   return hipSuccess;
 }
 
+// Face-parallel scatters: the same event marks around all face kernels (there is no halo pass).
+template <typename T, bool VJP>
+hipError_t run_faces_marked(const DevPlan &p, const T *x, const T *u2, T *y, const T *tab, hipStream_t s) {
+  mark(p, 0, s);
+  const hipError_t e = run_faces<T, VJP>(p, x, u2, y, tab, s);
+  mark(p, 1, s);
+  mark(p, 2, s);
+  return e;
+}
+
 }  // namespace
 
 hipError_t launch_apply_f64(const DevPlan &p, const double *u, double *y, bool accumulate, hipStream_t s) {
-  if (p.scatter == Scatter::Owner) return dispatch_box<double, false>(p, u, nullptr, y, p.tab64, accumulate, s);
+  if (p.scatter == Scatter::Box) return dispatch_box<double, false>(p, u, nullptr, y, p.tab64, accumulate, s);
   if (!accumulate) {
     hipError_t e = zero_support(p, y, s);
     if (e != hipSuccess) return e;
   }
-  return run_faces<double, false>(p, u, nullptr, y, p.tab64, s);
+  return run_faces_marked<double, false>(p, u, nullptr, y, p.tab64, s);
 }
 
 hipError_t launch_apply_f32(const DevPlan &p, const float *u, float *y, bool accumulate, hipStream_t s) {
-  if (p.scatter == Scatter::Owner) return dispatch_box<float, false>(p, u, nullptr, y, p.tab32, accumulate, s);
+  if (p.scatter == Scatter::Box) return dispatch_box<float, false>(p, u, nullptr, y, p.tab32, accumulate, s);
   if (!accumulate) {
     hipError_t e = zero_support(p, y, s);
     if (e != hipSuccess) return e;
   }
-  return run_faces<float, false>(p, u, nullptr, y, p.tab32, s);
+  return run_faces_marked<float, false>(p, u, nullptr, y, p.tab32, s);
 }
 
 hipError_t launch_vjp(const DevPlan &p, const double *u, const double *w, double *du, double *dgamma,
                       bool accumulate, hipStream_t s) {
-  const bool owner = p.scatter == Scatter::Owner;
-  const int n_parts = owner ? p.n_boxes : p.n_batches;
+  const bool box = p.scatter == Scatter::Box;
+  const int n_parts = box ? p.n_boxes : p.n_batches;
   hipError_t e = hipSuccess;
-  if (owner) {
+  if (box) {
     e = dispatch_box<double, true>(p, w, u, du, p.tab64, accumulate, s);
   } else {
     if (!accumulate) e = zero_support(p, du, s);
-    if (e == hipSuccess) e = run_faces<double, true>(p, w, u, du, p.tab64, s);
+    if (e == hipSuccess) e = run_faces_marked<double, true>(p, w, u, du, p.tab64, s);
   }
   if (e != hipSuccess) return e;
   if (n_parts == 0) {

@@ -29,10 +29,10 @@ class GhostOperator:
     host-only plan (inspection without a GPU).
     """
 
-    SCATTERS = ("owner", "atomic", "coloured")
+    SCATTERS = ("box", "atomic", "coloured")
 
     def __init__(self, d, n, lo, h, k, gamma, centre=None, radius=None, cell_class=None,
-                 scatter="owner", device=0):
+                 scatter="box", device=0):
         lib = L.load()
         mesh = L.GhostMesh()
         mesh.dim = d
@@ -55,7 +55,7 @@ class GhostOperator:
         g = (ctypes.c_double * k)(*[float(x) for x in gamma])
         if scatter not in self.SCATTERS:
             raise ValueError(f"scatter must be one of {self.SCATTERS}")
-        flags = L.GHOST_FP64 | L.GHOST_FP32 | {"owner": 0, "atomic": L.GHOST_ATOMIC,
+        flags = L.GHOST_FP64 | L.GHOST_FP32 | {"box": 0, "atomic": L.GHOST_ATOMIC,
                                                "coloured": L.GHOST_COLOURED}[scatter]
         self.scatter = scatter
         handle = ctypes.c_void_p()
@@ -71,7 +71,7 @@ class GhostOperator:
         self.n_lattice = self.stats["n_lattice"]
 
     @classmethod
-    def from_workload(cls, w, scatter="owner", device=0, gamma=None):
+    def from_workload(cls, w, scatter="box", device=0, gamma=None):
         return cls(w.d, w.n, w.lo, w.h, w.k, w.gamma() if gamma is None else gamma,
                    centre=w.centre, radius=w.radius, scatter=scatter, device=device)
 
@@ -194,6 +194,17 @@ class GhostOperator:
         L.check(self._lib.ghost_box_layout(self._h, None, 0, None, 0,
                                            runs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nr))
         return boxes, visits[:nv], runs[:nr]
+
+    def set_timing(self, on=True):
+        """Record per-kernel HIP events in later applies / VJPs (see kernel_times)."""
+        L.check(self._lib.ghost_set_timing(self._h, 1 if on else 0))
+
+    def kernel_times(self):
+        """Summed durations (ms) of the scatter kernels and of the halo pass over the calls recorded
+        since the last read, and the number of calls; waits for the recorded events."""
+        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        L.check(self._lib.ghost_kernel_times(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)))
+        return {"main_ms": a.value, "halo_ms": b.value, "calls": n.value}
 
     def tables(self):
         k = self.k

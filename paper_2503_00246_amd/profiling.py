@@ -91,7 +91,7 @@ def main():
     b.add_argument("fetch_dir")
     b.add_argument("write_dir")
     b.add_argument("key", help="workload/scatter/precision key for the traffic file")
-    b.add_argument("--kernel", default="owner_kernel<double")
+    b.add_argument("--kernel", default="box_kernel<double")
     b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--out", default=None)
     a = ap.parse_args()

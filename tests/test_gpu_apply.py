@@ -31,10 +31,10 @@ def nerr(y, ref):
     return float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
 
 
-SCATTERS = ("owner", "atomic", "coloured")
+SCATTERS = ("box", "atomic", "coloured")
 
 
-def gpu_op(w, scatter="owner"):
+def gpu_op(w, scatter="box"):
     from paper_2503_00246_amd.operator import GhostOperator
     return GhostOperator.from_workload(w, scatter=scatter)
 
@@ -151,6 +151,32 @@ def test_zero_faces_is_noop(scatter):
     du, dg = op.vjp(u, u)
     torch.cuda.synchronize()
     assert float((y - 2.0).abs().max()) == 0.0 and float(du.abs().max()) == 0.0 and float(dg.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("scatter", SCATTERS)
+def test_kernel_timing_records_every_call(scatter):
+    """With per-kernel timing on, each apply / VJP records one event triple on the apply's stream; the
+    results are the same as without it, and contexts without faces record (empty) intervals too."""
+    w = WORKLOADS["ball3d_q3_64"]
+    op = gpu_op(w, scatter)
+    u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda()
+    ref = op.apply(u)
+    op.set_timing(True)
+    y = op.apply(u)
+    op.apply_f32(u.float())
+    op.vjp(u, u)
+    op.set_timing(False)
+    op.apply(u)
+    t = op.kernel_times()
+    assert t["calls"] == 3 and t["main_ms"] > 0 and t["halo_ms"] >= 0
+    assert op.kernel_times()["calls"] == 0
+    assert torch.equal(y, ref) or nerr(y.cpu().numpy(), ref.cpu().numpy()) <= TOL64
+    from paper_2503_00246_amd.operator import GhostOperator
+    empty = GhostOperator(3, (8, 8, 8), (-1, -1, -1), 0.25, 3, [1.0, 1.0, 1.0], centre=(9.0, 9.0, 9.0), radius=0.5,
+                          scatter=scatter)
+    empty.set_timing(True)
+    empty.apply(torch.ones(empty.n_lattice, dtype=torch.float64, device="cuda"))
+    assert empty.kernel_times()["calls"] == 1
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

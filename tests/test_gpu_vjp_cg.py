@@ -22,7 +22,7 @@ def oracle(w, per_face=False):
     return GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), centre=w.centre, radius=w.radius, per_face=per_face)
 
 
-@pytest.mark.parametrize("scatter", ["owner", "atomic", "coloured"])
+@pytest.mark.parametrize("scatter", ["box", "atomic", "coloured"])
 def test_vjp_matches_oracle_gradient_on_submesh(scatter):
     """16^3 block of the 96^3 Q4 mesh: the oracle's exact sparse gradients of L = 0.5|G u - t|^2."""
     w = submesh_q4_16()
