@@ -44,6 +44,7 @@ def _compile(src):
                "-c", path, "-o", obj] + _common()
     else:
         cmd = [hipcc, "-x", "hip", "--offload-arch=gfx950", "-munsafe-fp-atomics",
+               "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-c", path, "-o", obj] + _common()
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -24,6 +24,8 @@ constexpr int box_acc(int dim) { return dim == 3 ? box_pitch(3) * 16 * 16 : box_
 // split into several boxes over the same node box).
 constexpr int kBoxThreads = 512;
 constexpr int kMaxBoxVisits = kBoxThreads;
+// halo slots of one box, numbered from the box's first (a box touches at most its 16^3 / 64^2 nodes)
+constexpr int kMaxBoxHalo = 1 << 13;
 
 // Threads per face: one per tangential node line, (k+1)^(d-1).
 constexpr int lines_per_face(int dim, int k) { return dim == 3 ? (k + 1) * (k + 1) : (k + 1); }

@@ -250,6 +250,29 @@ __device__ __forceinline__ VisitPrep prep_visit(Visit vis, bool live, int t1, in
   return q;
 }
 
+// The 2k+1 patch values of a normal line.  A line along x (stride 1) is read in 16-byte pieces:
+// a wave of x-normal faces then touches each cache line of its rows once per piece instead of once
+// per value.  (The pieces are only 8-byte aligned; gfx9 global loads accept that.)
+template <typename T, int NN>
+__device__ __forceinline__ void gather_line(const T *__restrict__ base, uint32_t gofs, uint32_t sn, T (&out)[NN]) {
+  if (sn == 1) {
+    constexpr int W = 16 / (int)sizeof(T);
+    typedef T V __attribute__((ext_vector_type(W), aligned(sizeof(T))));
+    const V *p = reinterpret_cast<const V *>(base + gofs);
+#pragma unroll
+    for (int q = 0; q < NN / W; ++q) {
+      const V v = p[q];
+#pragma unroll
+      for (int e = 0; e < W; ++e) out[q * W + e] = v[e];
+    }
+#pragma unroll
+    for (int i = (NN / W) * W; i < NN; ++i) out[i] = base[gofs + i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NN; ++i) out[i] = base[gofs + i * sn];
+  }
+}
+
 template <int D>
 using LineMask = typename std::conditional<D == 3, uint32_t, uint64_t>::type;
 __device__ __forceinline__ int popc_mask(uint32_t m) { return __popc(m); }
@@ -268,14 +291,19 @@ __device__ __forceinline__ __attribute__((address_space(3))) void *lds_ptr(char 
 // s_waitcnt immediate: vector-memory count 0, the other counters left at their maximum.
 constexpr int kWaitVmcnt0 = (7 << 4) | (15 << 8);
 
-__device__ __forceinline__ int take_box(BoxSched *s, int grp, int lo, int hi, int nblk) {
-  const int t = atomicAdd(&s->ctr[grp], 1);
+// A ticket is drawn in two steps so that the atomic's latency overlaps work: draw_ticket issues it,
+// settle_ticket (called once its result is needed) maps it to a box or to -1 past the range.
+__device__ __forceinline__ int draw_ticket(BoxSched *s, int grp) { return atomicAdd(&s->ctr[grp], 1); }
+__device__ __forceinline__ int settle_ticket(BoxSched *s, int grp, int t, int lo, int hi, int nblk) {
   if (lo + t < hi) return lo + t;
   if (atomicAdd(&s->done[grp], 1) == nblk - 1) {
     atomicExch(&s->ctr[grp], 0);
     atomicExch(&s->done[grp], 0);
   }
   return -1;
+}
+__device__ __forceinline__ int take_box(BoxSched *s, int grp, int lo, int hi, int nblk) {
+  return settle_ticket(s, grp, draw_ticket(s, grp), lo, hi, nblk);
 }
 
 // Lattice index of a box's origin, and the offset (<= 0) from it of the gather base: the lowest node a
@@ -289,7 +317,7 @@ __device__ __forceinline__ int gather_low(int o0, int o1, int o2, int k, int s1,
 
 // Box fields as wave-uniform scalars.
 struct BoxScalars {
-  int o0, o1, o2, visit_first, visit_count, line_first, line_count;
+  int o0, o1, o2, visit_first, visit_count, line_first, line_count, halo_first;
 };
 __device__ __forceinline__ BoxScalars load_box(const Box *__restrict__ boxes, int b) {
   const Box *bp = boxes + __builtin_amdgcn_readfirstlane(b);
@@ -301,6 +329,7 @@ __device__ __forceinline__ BoxScalars load_box(const Box *__restrict__ boxes, in
   r.visit_count = __builtin_amdgcn_readfirstlane(bp->visit_count);
   r.line_first = __builtin_amdgcn_readfirstlane(bp->line_first);
   r.line_count = __builtin_amdgcn_readfirstlane(bp->line_count);
+  r.halo_first = __builtin_amdgcn_readfirstlane(bp->halo_first);
   return r;
 }
 
@@ -380,15 +409,8 @@ __device__ __forceinline__ void box_body(
   VisitPrep nxp = prep_visit<D, K>(in_block && f < bc.visit_count ? svis[0][f] : Visit(0),
                                    in_block && f < bc.visit_count, t1, t2, s1, s2, bc.o0, bc.o1, bc.o2, glo);
   T lnext[NN], unext[NN];
-  {
-    const T *xg = x + (box_base + glo);
-    const T *ug = VJP ? u2 + (box_base + glo) : nullptr;
-#pragma unroll
-    for (int i = 0; i < NN; ++i) {
-      lnext[i] = xg[nxp.gofs + i * nxp.sn];
-      if (VJP) unext[i] = ug[nxp.gofs + i * nxp.sn];
-    }
-  }
+  gather_line<T, NN>(x + (box_base + glo), nxp.gofs, nxp.sn, lnext);
+  if (VJP) gather_line<T, NN>(u2 + (box_base + glo), nxp.gofs, nxp.sn, unext);
   int buf = 0;
 
   for (;;) {
@@ -402,25 +424,31 @@ __device__ __forceinline__ void box_body(
       bn = load_box(boxes, nxt);
       nglo = gather_low(bn.o0, bn.o1, bn.o2, k, s1, s2, nbase);
     }
-    for (int i = tid; i < ACC; i += kBoxThreads) acc[i] = A(0);
-    // Per flush line: fa = accumulator byte offset | shared << 16 (-1: the lane's node is not touched);
-    // fs = y offset from the box origin (exclusive node) or halo slot (shared node).
-    int fa[kLines], fs[kLines];
+    int ticket = 0;  // draws the box after `nxt` (thread 0); settled at the end of this box
+    if (tid == 0 && nxt >= 0) ticket = draw_ticket(sched, sg);
 #pragma unroll
-    for (int m = 0; m < kLines; ++m) {
-      const BoxLine bl = slines[grp + m * kGroups];
-      const Mask tm = (Mask)bl.touched, sm = (Mask)bl.shared;
-      const bool touched = grp + m * kGroups < bc.line_count && (tm & gbit);
-      const bool sh = (sm & gbit) != 0;
-      const int ry = bl.line % E, rz = bl.line / E;
-      fa[m] = touched ? ((int)sizeof(A) * (gx + P * bl.line) | (sh ? 1 << 16 : 0)) : -1;
-      fs[m] = sh ? bl.slot_base + popc_mask(sm & (gbit - 1)) : gx + s1 * ry + s2 * rz;
+    for (int i = 0; i < (ACC + kBoxThreads - 1) / kBoxThreads; ++i)
+      if (i * kBoxThreads + tid < ACC) acc[i * kBoxThreads + tid] = A(0);
+    // Per flush line, one packed word: -1 when the lane's node is not touched, else the box line index
+    // (bits 0-7), a shared flag (bit 8) and, for a shared node, its halo slot relative to the box's
+    // first (bits 9-21).  All records are read before any is decoded, and the decode has no branches.
+    int fl[kLines];
+    {
+      BoxLine bl[kLines];
+#pragma unroll
+      for (int m = 0; m < kLines; ++m) bl[m] = slines[grp + m * kGroups];
+#pragma unroll
+      for (int m = 0; m < kLines; ++m) {
+        const Mask tm = (Mask)bl[m].touched, sm = (Mask)bl[m].shared;
+        const bool touched = grp + m * kGroups < bc.line_count && (tm & gbit) != 0;
+        const bool sh = (sm & gbit) != 0;
+        const int rel = bl[m].slot_base - bc.halo_first + popc_mask(sm & (gbit - 1));
+        fl[m] = touched ? (bl[m].line | (sh ? (1 << 8) | (rel << 9) : 0)) : -1;
+      }
     }
     double pj[k];
 #pragma unroll
     for (int j = 0; j < k; ++j) pj[j] = 0.0;
-    int after = -1;  // the box after `nxt` (thread 0)
-    if (tid == 0 && nxt >= 0) after = take_box(sched, sg, lo, hi, nblk);
     __syncthreads();  // acc zeroed before any add; slines read before it is refilled
     // Copy the next box's visits and line records straight from global memory into LDS (16 bytes per
     // lane, no registers held); the last batch of this box waits for the copies before its barrier.
@@ -497,7 +525,11 @@ __device__ __forceinline__ void box_body(
       __syncthreads();
       if (last && accumulate) {  // y at the exclusive flush nodes
 #pragma unroll
-        for (int m = 0; m < kLines; ++m) yv[m] = yb[(uint32_t)(fa[m] >= 0 && fa[m] < (1 << 16) ? fs[m] : 0)];
+        for (int m = 0; m < kLines; ++m) {
+          const unsigned line = (unsigned)fl[m] & 0xFF;
+          const bool excl = fl[m] >= 0 && !(fl[m] & (1 << 8));
+          yv[m] = yb[excl ? (uint32_t)(gx + s1 * (int)(line % E) + s2 * (int)(line / E)) : 0u];
+        }
       }
       // issue the next gather: the next batch of this box, or the first batch of the next box
       if (!last || nxt >= 0) {
@@ -508,13 +540,8 @@ __device__ __forceinline__ void box_body(
         const int64_t gb = last ? nbase + nglo : box_base + glo;
         nxp = last ? prep_visit<D, K>(v, live, t1, t2, s1, s2, bn.o0, bn.o1, bn.o2, nglo)
                    : prep_visit<D, K>(v, live, t1, t2, s1, s2, bc.o0, bc.o1, bc.o2, glo);
-        const T *xg = x + gb;
-        const T *ug = VJP ? u2 + gb : nullptr;
-#pragma unroll
-        for (int i = 0; i < NN; ++i) {
-          lnext[i] = xg[nxp.gofs + i * nxp.sn];
-          if (VJP) unext[i] = ug[nxp.gofs + i * nxp.sn];
-        }
+        gather_line<T, NN>(x + gb, nxp.gofs, nxp.sn, lnext);
+        if (VJP) gather_line<T, NN>(u2 + gb, nxp.gofs, nxp.sn, unext);
       }
       // tangential masses in place: each row (column) is read and rewritten by the one thread that owns
       // it, and the barrier between the passes orders the row writes before the column reads
@@ -611,13 +638,14 @@ __device__ __forceinline__ void box_body(
     // flush: exclusive nodes to y, shared ones to their halo slot
 #pragma unroll
     for (int m = 0; m < kLines; ++m) {
-      if (fa[m] >= 0) {
-        A v = *reinterpret_cast<const A *>(accb + (fa[m] & 0xFFFF));
-        if (fa[m] >> 16) {
-          halo[fs[m]] = (T)v;
+      if (fl[m] >= 0) {
+        const unsigned line = (unsigned)fl[m] & 0xFF;
+        A v = acc[gx + P * (int)line];
+        if (fl[m] & (1 << 8)) {
+          halo[bc.halo_first + (fl[m] >> 9)] = (T)v;
         } else {
           if (accumulate) v += (A)yv[m];
-          yb[(uint32_t)fs[m]] = (T)v;
+          yb[(uint32_t)(gx + s1 * (int)(line % E) + s2 * (int)(line / E))] = (T)v;
         }
       }
     }
@@ -639,7 +667,7 @@ __device__ __forceinline__ void box_body(
         partial[(int64_t)cur * k + tid] = sum;
       }
     }
-    if (tid == 0) s_box[0] = after;
+    if (tid == 0) s_box[0] = nxt >= 0 ? settle_ticket(sched, sg, ticket, lo, hi, nblk) : -1;
     __syncthreads();  // acc read by the flush before the next zeroing; s_box published
     if (nxt < 0) break;
     cur = nxt;

@@ -567,14 +567,20 @@ std::string build_box_layout(Plan &p) {
     for (int a = 0; a < 3; ++a) bx.org[a] = a < d ? (int32_t)(kB * bb[a]) : 0;
     bx.visit_first = (int32_t)p.visits.size();
     bx.visit_count = (int32_t)t.v.size();
-    {
-      const size_t nv = t.v.size(), nbatch = (nv + fpb - 1) / fpb;
+    // visits grouped by normal axis (x first: a wave whose faces all have their normal along x gathers
+    // contiguous lines with 16-byte loads), each group interleaved as described above
+    for (int a = 0; a < d; ++a) {
+      std::vector<Visit> g;
+      for (Visit v : t.v)
+        if ((int)((v >> 60) & 3) == a) g.push_back(v);
+      const size_t nv = g.size(), nbatch = (nv + fpb - 1) / fpb;
       for (size_t q = 0; q < nbatch; ++q)
         for (size_t r = 0; r < fpb; ++r)
-          if (q + r * nbatch < nv) p.visits.push_back(t.v[q + r * nbatch]);
+          if (q + r * nbatch < nv) p.visits.push_back(g[q + r * nbatch]);
     }
     bx.run_first = (int32_t)p.box_runs.size();
     bx.line_first = (int32_t)p.box_lines.size();
+    bx.halo_first = (int32_t)slots;
     for (const Run &r : t.runs) {
       const int64_t line = r.start / p.L[0], x0 = r.start % p.L[0];
       const int64_t Y = line % p.L[1], Z = line / p.L[1];
@@ -616,8 +622,8 @@ std::string build_box_layout(Plan &p) {
     // and one lane group per box line: a box has at least one of each, at most kMaxBoxVisits visits
     // and at most one line per (y, z) of its node box
     if (bx.visit_count < 1 || bx.visit_count > kMaxBoxVisits || bx.line_count < 1 ||
-        bx.line_count > (d == 3 ? E * E : E))
-      return "box layout: a box without visits or lines, or with more visits or lines than it holds";
+        bx.line_count > (d == 3 ? E * E : E) || slots - bx.halo_first > kMaxBoxHalo)
+      return "box layout: a box without visits or lines, or with more visits, lines or halo slots than it holds";
     p.boxes.push_back(bx);
   }
   if (slots >= ((int64_t)1 << 31) || (int64_t)p.visits.size() >= ((int64_t)1 << 31))

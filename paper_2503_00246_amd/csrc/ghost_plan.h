@@ -35,10 +35,11 @@ struct Box {
   int32_t visit_first, visit_count;
   int32_t run_first, run_count;   // inspection runs (BoxRun)
   int32_t line_first, line_count; // device form: touched x-lines of the box (BoxLine)
+  int32_t halo_first;             // first halo slot of the box (its slots are consecutive)
 };
 
 // One touched x-line of a box node box: bit x of `touched` marks box node x of the line as a node the
-// brick contributes to; bit x of `shared` marks it as lying on a box face shared with another brick
+// box contributes to; bit x of `shared` marks it as a node another box touches too
 // (its value goes to halo slot slot_base + (number of shared bits below x) instead of y).
 struct BoxLine {
   uint64_t touched, shared;
