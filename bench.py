@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="one JSON line per degree/mesh of the roofline sweep")
+    ap.add_argument("--mode", default="apply", choices=["apply", "vjp", "cg"],
+                    help="apply: the benchmark line; vjp: ghost_vjp on ball3d_q4_96; cg: FP64 vs mixed CG on "
+                         "ball3d_q7_96 (extra lines, not the benchmark metric)")
+    ap.add_argument("--cg-max-iter", type=int, default=5000)
     ap.add_argument("--traffic", default=TRAFFIC_FILE, help="JSON file with measured HBM bytes per launch")
     return ap.parse_args()
 
@@ -140,6 +144,65 @@ def run_workload(w, args, with_cpu):
     return out
 
 
+def run_vjp(w, args):
+    """ghost_vjp (du = G w and dgamma) timed like the apply; box-kernel bytes: u and w read on the
+    support, du written on the exclusive nodes (overwrite mode)."""
+    import torch
+    from paper_2503_00246_amd.operator import GhostOperator
+    from paper_2503_00246_amd.workloads import SEED_T, SEED_U, uniform_vector
+
+    op = GhostOperator.from_workload(w, scatter=args.scatter)
+    st = op.stats
+    u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda()
+    wv = torch.from_numpy(uniform_vector(w.n_lattice, SEED_T)).cuda()
+    du = torch.zeros_like(u)
+    fn = lambda: op.vjp(u, wv, du=du, accumulate=False)
+    for _ in range(args.warmup):
+        fn()
+    torch.cuda.synchronize()
+    op.kernel_times()
+    op.set_timing(True)
+    t = timed_applies(fn, args.steps, 0)
+    op.set_timing(False)
+    kt = op.kernel_times()
+    box_t = kt["main_ms"] / 1e3 / kt["calls"]
+    n_sup, n_ex = st["n_support_dofs"], st["n_support_dofs"] - st["n_halo_nodes"]
+    alg = 16 * n_sup + 8 * n_ex
+    print(json.dumps({"metric": "ghost_vjp patch DoFs/s (GDoF/s), FP64", "workload": w.name,
+                      "value": round(st["n_faces_total"] * st["n_patch_dofs"] / t / 1e9, 4), "unit": "GDoF/s",
+                      "ms_per_step": round(t * 1e3, 5), "steps": args.steps,
+                      "box_kernel_us": round(box_t * 1e6, 2), "halo_pass_us": round(kt["halo_ms"] / kt["calls"] * 1e3, 2),
+                      "roofline": {"bound": "hbm", "achieved": round(alg / box_t / 1e9, 2), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(alg / box_t / 1e9 / HBM_PEAK_GBS, 4),
+                                   "bytes_per_launch": alg}}), flush=True)
+
+
+def run_cg(w, args):
+    """(M_h + G) x = b to a relative true residual of 1e-10: pure FP64 CG vs FP64-outer / FP32-inner CG,
+    unpreconditioned and with the Jacobi preconditioner (one JSON line per preconditioner)."""
+    import time as _time
+    import torch
+    from paper_2503_00246_amd.operator import GhostOperator
+    from paper_2503_00246_amd.workloads import SEED_B, uniform_vector
+
+    op = GhostOperator.from_workload(w, scatter=args.scatter)
+    diag = op.mass_diag()
+    b = torch.from_numpy(uniform_vector(w.n_lattice, SEED_B)).cuda()
+    b = torch.where(diag > 0, b, torch.zeros_like(b))
+    for precond in ("none", "jacobi"):
+        out = {"metric": "CG on (M_h + G) x = b to 1e-10 relative true residual", "workload": w.name,
+               "precond": precond, "active_dofs": int((diag > 0).sum()), "max_iter": args.cg_max_iter}
+        for mode in ("fp64", "mixed"):
+            op.cg(b, mode=mode, tol=1e-4, max_iter=20, precond=precond)  # warm-up: workspace, kernels
+            torch.cuda.synchronize()
+            t0 = _time.perf_counter()
+            x, res = op.cg(b, mode=mode, tol=1e-10, max_iter=args.cg_max_iter, precond=precond)
+            torch.cuda.synchronize()
+            out[mode] = {"seconds": round(_time.perf_counter() - t0, 4), **res}
+        out["mixed_speedup"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+        print(json.dumps(out), flush=True)
+
+
 def box_bytes(st, elem):
     """Algorithmic bytes of one box-kernel launch: u on the support, y read and written on the nodes
     no other box touches (the halo pass reads and writes y on the others)."""
@@ -155,6 +218,12 @@ def main():
     import torch
     from paper_2503_00246_amd.workloads import WORKLOADS, sweep_workload
 
+    if args.mode == "vjp":
+        run_vjp(WORKLOADS["ball3d_q4_96" if args.workload == "ball3d_q5_128" else args.workload], args)
+        return
+    if args.mode == "cg":
+        run_cg(WORKLOADS["ball3d_q7_96" if args.workload == "ball3d_q5_128" else args.workload], args)
+        return
     if args.sweep:
         for k, n in [(3, 128), (3, 96), (4, 96), (5, 96), (5, 128), (6, 96), (7, 96)]:
             w = sweep_workload(k, n)

@@ -165,6 +165,15 @@ int ghost_vjp(ghost_ctx *ctx, const double *u, const double *w, double *du, doub
  */
 int ghost_mass_diag(ghost_ctx *ctx, double *diag, void *stream);
 
+/*
+ * diag (+)= the diagonal of G (§2.4: for a patch node at normal position i and tangential
+ * positions t, sum_j gamma_j h^{d-1-2j} g_j[i]^2 times the diagonal mass entries), summed over
+ * the faces, for the current gamma.  diag: DEVICE array of n_lattice doubles; accumulate = 0 zeroes
+ * the support first (other entries untouched).  Stream-ordered; uses FP64 atomics (meant for
+ * preconditioner set-up, not for the hot loop).
+ */
+int ghost_diag(ghost_ctx *ctx, double *diag, int accumulate, void *stream);
+
 /* Conjugate gradients on (M + G) x = b over the active nodes (M as in ghost_mass_diag). */
 #define GHOST_CG_FP64 0  /* plain FP64 CG */
 #define GHOST_CG_MIXED 1 /* FP64 outer refinement of the true residual, FP32 inner CG */
@@ -174,8 +183,12 @@ typedef struct {
   double tol;        /* stop when |b - A x|_2 <= tol |b|_2 (true residual, FP64) */
   int max_iter;      /* cap on the total number of (inner) iterations */
   double inner_tol;  /* mixed: relative residual reduction of each inner solve */
-  int check_every;   /* FP64 mode: recompute the true residual every this many iterations */
+  int check_every;   /* recompute the true residual every this many iterations (FP64 mode, and
+                        every FP64 / Jacobi-preconditioned stopping test) */
+  int precond;       /* GHOST_CG_NONE or GHOST_CG_JACOBI */
 } ghost_cg_opts;
+#define GHOST_CG_NONE 0   /* unpreconditioned */
+#define GHOST_CG_JACOBI 1 /* diagonal of M + G (computed on the device for the current gamma) */
 
 typedef struct {
   int iterations;          /* total (inner) iterations */

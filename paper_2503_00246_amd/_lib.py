@@ -14,10 +14,11 @@ GHOST_KMAX = 7
 GHOST_LS_BALL, GHOST_LS_CELLS = 0, 1
 GHOST_FP64, GHOST_FP32, GHOST_COLOURED, GHOST_ATOMIC = 1, 2, 4, 8
 GHOST_CG_FP64, GHOST_CG_MIXED = 0, 1
+GHOST_CG_NONE, GHOST_CG_JACOBI = 0, 1
 
 EXPORTS = ["ghost_setup", "ghost_set_gamma", "ghost_apply", "ghost_apply_f32", "ghost_vjp",
            "ghost_mass_diag", "ghost_cg", "ghost_info", "ghost_faces", "ghost_tables", "ghost_box_layout",
-           "ghost_destroy", "ghost_last_error", "ghost_set_timing", "ghost_kernel_times"]
+           "ghost_destroy", "ghost_last_error", "ghost_set_timing", "ghost_kernel_times", "ghost_diag"]
 
 
 class GhostMesh(ctypes.Structure):
@@ -52,7 +53,7 @@ class GhostStats(ctypes.Structure):
 
 class GhostCgOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("inner_tol", ctypes.c_double), ("check_every", ctypes.c_int)]
+                ("inner_tol", ctypes.c_double), ("check_every", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class GhostCgResult(ctypes.Structure):
@@ -86,6 +87,7 @@ def load(path=LIB_PATH):
     lib.ghost_apply_f32.argtypes = [P, P, P, c_int, P]
     lib.ghost_vjp.argtypes = [P, P, P, P, P, c_int, P]
     lib.ghost_mass_diag.argtypes = [P, P, P]
+    lib.ghost_diag.argtypes = [P, P, c_int, P]
     lib.ghost_cg.argtypes = [P, P, P, ctypes.POINTER(GhostCgOpts), ctypes.POINTER(GhostCgResult), P]
     lib.ghost_info.argtypes = [P, ctypes.POINTER(GhostStats)]
     lib.ghost_faces.argtypes = [P, c_int, ctypes.POINTER(ctypes.c_int32), c_i64]

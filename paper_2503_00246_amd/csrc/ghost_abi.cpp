@@ -403,6 +403,17 @@ int ghost_kernel_times(ghost_ctx *ctx, double *main_ms, double *halo_ms, int64_t
   return GHOST_OK;
 }
 
+int ghost_diag(ghost_ctx *ctx, double *diag, int accumulate, void *stream) {
+  if (!ctx || !diag) return fail(GHOST_EINVAL, "null context or diag");
+  if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  hipError_t e = hipSuccess;
+  if (!accumulate) e = ghost::launch_zero_support(ctx->dev, diag, static_cast<hipStream_t>(stream));
+  if (e == hipSuccess) e = ghost::launch_ghost_diag(ctx->dev, diag, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GHOST_OK : fail_hip(e, "diag launch");
+}
+
 int ghost_mass_diag(ghost_ctx *ctx, double *diag, void *stream) {
   if (!ctx || !diag) return fail(GHOST_EINVAL, "null context or diag");
   if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");
@@ -510,6 +521,8 @@ int ghost_cg(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts *op
   if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");
   if (b == x) return fail(GHOST_EINVAL, "b and x must differ");
   if (opts->mode != GHOST_CG_FP64 && opts->mode != GHOST_CG_MIXED) return fail(GHOST_EINVAL, "unknown CG mode");
+  if (opts->precond != GHOST_CG_NONE && opts->precond != GHOST_CG_JACOBI)
+    return fail(GHOST_EINVAL, "unknown CG preconditioner");
   if (!(opts->tol > 0) || opts->max_iter < 1) return fail(GHOST_EINVAL, "tol must be > 0 and max_iter >= 1");
   if (opts->mode == GHOST_CG_MIXED && !(opts->inner_tol > 0 && opts->inner_tol < 1))
     return fail(GHOST_EINVAL, "inner_tol must be in (0, 1)");

@@ -6,7 +6,9 @@
 //
 // FP64 mode: plain CG from x = 0.  The recursive residual is replaced by the true one,
 // b - A x, every check_every iterations and whenever it meets the tolerance; the solve
-// stops on the true residual.
+// stops on the true residual.  With the Jacobi preconditioner (1 / diag(M + G), built per
+// solve) the CG is the preconditioned one and the true residual is tested every
+// check_every iterations.
 // Mixed mode: outer refinement in FP64 (true residual r = b - A x with the FP64 apply,
 // x += e), inner CG on A e = r with FP32 vectors, FP32 ghost apply and FP32 mass, and
 // FP64 dot products and scalars, run until its residual drops by inner_tol.
@@ -55,31 +57,39 @@ __device__ __forceinline__ void block_partial(double v, double *partial) {
   if (seg < n_segs) sg = segs[seg];                                   \
   for (int i = lane; i < sg.len; i += 64)
 
-// x = 0, r = (T) src, p = r; partial <r, r>
+// With a preconditioner, z = dinv * r (Jacobi); without one (dinv null), z = r.
 template <typename T>
-__global__ void start_kernel(const Run *segs, int n_segs, const double *src, T *x, T *r, T *p, double *partial) {
+__device__ __forceinline__ T precond(const T *dinv, int64_t j, T r) {
+  return dinv ? dinv[j] * r : r;
+}
+
+// x = 0, r = (T) src, p = z; partial <r, z>
+template <typename T>
+__global__ void start_kernel(const Run *segs, int n_segs, const double *src, T *x, T *r, T *p, const T *dinv,
+                             double *partial) {
   double acc = 0.0;
   SEG_LOOP {
     const int64_t j = sg.start + i;
     const T v = (T)src[j];
+    const T z = precond(dinv, j, v);
     x[j] = T(0);
     r[j] = v;
-    p[j] = v;
-    acc += (double)v * (double)v;
+    p[j] = z;
+    acc += (double)v * (double)z;
   }
   block_partial(acc, partial);
 }
 
-// optionally p = r + beta p, then q = mdiag * p
+// optionally p = z + beta p, then q = mdiag * p
 template <typename T>
-__global__ void pq_kernel(const Run *segs, int n_segs, T *p, const T *r, T *q, const T *mdiag,
+__global__ void pq_kernel(const Run *segs, int n_segs, T *p, const T *r, T *q, const T *mdiag, const T *dinv,
                           const double *scal, int update_p) {
   const T beta = (T)scal[S_BETA];
   SEG_LOOP {
     const int64_t j = sg.start + i;
     T pv = p[j];
     if (update_p) {
-      pv = r[j] + beta * pv;
+      pv = precond(dinv, j, r[j]) + beta * pv;
       p[j] = pv;
     }
     q[j] = mdiag[j] * pv;
@@ -96,10 +106,10 @@ __global__ void dot_kernel(const Run *segs, int n_segs, const T *a, const T *b, 
   block_partial(acc, partial);
 }
 
-// x += alpha p, r -= alpha q; partial <r, r>
+// x += alpha p, r -= alpha q; partial <r, z>
 template <typename T>
-__global__ void xr_kernel(const Run *segs, int n_segs, T *x, T *r, const T *p, const T *q, const double *scal,
-                          double *partial) {
+__global__ void xr_kernel(const Run *segs, int n_segs, T *x, T *r, const T *p, const T *q, const T *dinv,
+                          const double *scal, double *partial) {
   const T alpha = (T)scal[S_ALPHA];
   double acc = 0.0;
   SEG_LOOP {
@@ -107,9 +117,29 @@ __global__ void xr_kernel(const Run *segs, int n_segs, T *x, T *r, const T *p, c
     x[j] += alpha * p[j];
     const T rv = r[j] - alpha * q[j];
     r[j] = rv;
-    acc += (double)rv * (double)rv;
+    acc += (double)rv * (double)precond(dinv, j, rv);
   }
   block_partial(acc, partial);
+}
+
+// partial <r, dinv r>
+__global__ void rz_kernel(const Run *segs, int n_segs, const double *r, const double *dinv, double *partial) {
+  double acc = 0.0;
+  SEG_LOOP {
+    const int64_t j = sg.start + i;
+    acc += r[j] * dinv[j] * r[j];
+  }
+  block_partial(acc, partial);
+}
+
+// d = 1 / d on the active nodes (the Jacobi preconditioner from the diagonal of A), and its FP32 copy
+__global__ void invert_kernel(const Run *segs, int n_segs, double *d, float *d32) {
+  SEG_LOOP {
+    const int64_t j = sg.start + i;
+    const double v = 1.0 / d[j];
+    d[j] = v;
+    d32[j] = (float)v;
+  }
 }
 
 // q = mdiag * x (FP64), the mass part of A x
@@ -186,6 +216,8 @@ struct CgWork {
   int n_segs = 0, n_blocks = 0;
   double *mdiag = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *scal = nullptr, *partial = nullptr;
   float *mdiag32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *e32 = nullptr;
+  double *dinv = nullptr;  // Jacobi preconditioner 1 / diag(M + G), rebuilt per preconditioned solve
+  float *dinv32 = nullptr;
   double *host = nullptr;  // pinned, S_COUNT doubles
   std::vector<void *> allocs;
 };
@@ -234,6 +266,8 @@ hipError_t cg_init(ghost_ctx *ctx, CgWork **out, hipStream_t s) {
   if (e == hipSuccess) e = alloc(w, &w->p32, n);
   if (e == hipSuccess) e = alloc(w, &w->q32, n);
   if (e == hipSuccess) e = alloc(w, &w->e32, n);
+  if (e == hipSuccess) e = alloc(w, &w->dinv, n);
+  if (e == hipSuccess) e = alloc(w, &w->dinv32, n);
   if (e == hipSuccess) e = hipHostMalloc((void **)&w->host, S_COUNT * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = launch_mass_diag(dp, w->mdiag, s);
   if (e == hipSuccess) {
@@ -272,16 +306,21 @@ struct Runner {
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     return err == hipSuccess ? w->host[idx] : NAN;
   }
-  // r = b - A x (FP64), rr -> scal[mode target]; returns |r|^2
-  double true_residual(const double *b, const double *x, double *r) {
+  // r = b - A x (FP64); scal[RR] = <r, z> for the next CG step (z = dinv r, or r); returns |r|^2
+  double true_residual(const double *b, const double *x, double *r, const double *dinv) {
     hipLaunchKernelGGL(mass_kernel, grid, block, 0, s, w->segs, w->n_segs, x, (const double *)w->mdiag, w->q);
     check();
     if (err == hipSuccess) err = launch_apply_f64(dp, x, w->q, true, s);
     hipLaunchKernelGGL(residual_kernel, grid, block, 0, s, w->segs, w->n_segs, b, (const double *)w->q, r,
                        w->partial);
     check();
+    reduce(3);
+    if (dinv) {
+      hipLaunchKernelGGL(rz_kernel, grid, block, 0, s, w->segs, w->n_segs, (const double *)r, dinv, w->partial);
+      check();
+    }
     reduce(0);
-    return read(S_RR);
+    return read(S_TMP);
   }
 };
 
@@ -312,16 +351,30 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
   const double target = opts.tol * bnorm;
   int it = 0;
 
+  // Jacobi: dinv = 1 / (mass diagonal + diagonal of G) on the active nodes
+  const bool jac = opts.precond == GHOST_CG_JACOBI;
+  const double *dinv = jac ? w->dinv : nullptr;
+  const float *dinv32 = jac ? w->dinv32 : nullptr;
+  if (jac && R.err == hipSuccess) {
+    R.err = hipMemcpyAsync(w->dinv, w->mdiag, (size_t)host_plan(ctx).n_lattice * sizeof(double),
+                           hipMemcpyDeviceToDevice, s);
+    if (R.err == hipSuccess) R.err = launch_ghost_diag(dp, w->dinv, s);
+    hipLaunchKernelGGL(invert_kernel, grid, block, 0, s, w->segs, w->n_segs, w->dinv, w->dinv32);
+    R.check();
+  }
+
   if (opts.mode == GHOST_CG_FP64) {
-    hipLaunchKernelGGL(start_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, b, x, w->r, w->p, w->partial);
+    hipLaunchKernelGGL(start_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, b, x, w->r, w->p, dinv,
+                       w->partial);
     R.check();
     R.reduce(0);
-    double rr = R.read(S_RR);
+    double rr = R.read(S_RR);  // <r, z>
+    double rr_true = jac ? bnorm * bnorm : rr;
     const int every = opts.check_every > 0 ? opts.check_every : 50;
     bool update_p = false;
-    while (R.err == hipSuccess && std::sqrt(rr) > target && it < opts.max_iter) {
+    while (R.err == hipSuccess && std::sqrt(rr_true) > target && it < opts.max_iter) {
       hipLaunchKernelGGL(pq_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, w->p, (const double *)w->r,
-                         w->q, (const double *)w->mdiag, (const double *)w->scal, (int)update_p);
+                         w->q, (const double *)w->mdiag, dinv, (const double *)w->scal, (int)update_p);
       R.check();
       if (R.err == hipSuccess) R.err = launch_apply_f64(dp, w->p, w->q, true, s);
       hipLaunchKernelGGL(dot_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, (const double *)w->p,
@@ -329,15 +382,18 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
       R.check();
       R.reduce(1);
       hipLaunchKernelGGL(xr_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, x, w->r, (const double *)w->p,
-                         (const double *)w->q, (const double *)w->scal, w->partial);
+                         (const double *)w->q, dinv, (const double *)w->scal, w->partial);
       R.check();
       R.reduce(2);
       update_p = true;
       ++it;
-      rr = R.read(S_RR);
-      if (std::sqrt(rr) <= target || it % every == 0) {
+      if (!jac) {
+        rr = R.read(S_RR);  // without a preconditioner <r, z> = |r|^2: test the recursive residual
+        rr_true = rr;
+      }
+      if ((!jac && std::sqrt(rr) <= target) || it % every == 0) {
         // replace the recursive residual by the true one (the search direction is kept)
-        rr = R.true_residual(b, x, w->r);
+        rr_true = R.true_residual(b, x, w->r, dinv);
       }
     }
     res.outer = 1;
@@ -345,11 +401,11 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
     hipLaunchKernelGGL(add_kernel, grid, block, 0, s, w->segs, w->n_segs, x, (const float *)nullptr, 1);
     R.check();
     while (R.err == hipSuccess) {
-      const double rr_true = R.true_residual(b, x, w->r);
+      const double rr_true = R.true_residual(b, x, w->r, nullptr);
       if (!(std::sqrt(rr_true) > target) || it >= opts.max_iter) break;
       // inner FP32 CG on A e = r
       hipLaunchKernelGGL(start_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, (const double *)w->r, w->e32,
-                         w->r32, w->p32, w->partial);
+                         w->r32, w->p32, dinv32, w->partial);
       R.check();
       R.reduce(0);
       double rr = R.read(S_RR);
@@ -357,7 +413,7 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
       bool update_p = false;
       while (R.err == hipSuccess && std::sqrt(rr) > inner_target && it < opts.max_iter) {
         hipLaunchKernelGGL(pq_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, w->p32, (const float *)w->r32,
-                           w->q32, (const float *)w->mdiag32, (const double *)w->scal, (int)update_p);
+                           w->q32, (const float *)w->mdiag32, dinv32, (const double *)w->scal, (int)update_p);
         R.check();
         if (R.err == hipSuccess) R.err = launch_apply_f32(dp, w->p32, w->q32, true, s);
         hipLaunchKernelGGL(dot_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, (const float *)w->p32,
@@ -365,7 +421,7 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
         R.check();
         R.reduce(1);
         hipLaunchKernelGGL(xr_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, w->e32, w->r32,
-                           (const float *)w->p32, (const float *)w->q32, (const double *)w->scal, w->partial);
+                           (const float *)w->p32, (const float *)w->q32, dinv32, (const double *)w->scal, w->partial);
         R.check();
         R.reduce(2);
         update_p = true;
@@ -379,7 +435,7 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
     }
   }
   if (R.err != hipSuccess) return set_error(GHOST_EHIP, hipGetErrorString(R.err));
-  const double rr_final = R.true_residual(b, x, w->r);
+  const double rr_final = R.true_residual(b, x, w->r, nullptr);
   if (R.err != hipSuccess) return set_error(GHOST_EHIP, hipGetErrorString(R.err));
   res.iterations = it;
   res.rel_residual = bnorm > 0 ? std::sqrt(rr_final) / bnorm : 0.0;

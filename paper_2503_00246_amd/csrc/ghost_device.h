@@ -84,5 +84,7 @@ struct GammaArg {  // gamma by value, for host-side updates
 };
 hipError_t launch_set_gamma_host(const DevPlan &p, GammaArg g, hipStream_t s);
 hipError_t launch_mass_diag(const DevPlan &p, double *diag, hipStream_t s);
+hipError_t launch_ghost_diag(const DevPlan &p, double *diag, hipStream_t s);  // diag += diag(G)
+hipError_t launch_zero_support(const DevPlan &p, double *y, hipStream_t s);
 
 }  // namespace ghost

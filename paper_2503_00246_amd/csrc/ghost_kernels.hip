@@ -333,6 +333,24 @@ __device__ __forceinline__ BoxScalars load_box(const Box *__restrict__ boxes, in
   return r;
 }
 
+// Copy a box's visits and line records from global memory into LDS in 16-byte pieces, one per lane,
+// without holding them in registers (waves past the last piece issue nothing).
+template <int kLinesMax>
+__device__ __forceinline__ void copy_box_records(const Visit *__restrict__ visits, const BoxLine *__restrict__ lines,
+                                                 const BoxScalars &bn, Visit *svis_dst, BoxLine *slines_dst, int tid) {
+  constexpr int kVisitPieces = kMaxBoxVisits * (int)sizeof(Visit) / 16;
+  constexpr int kLinePieces = kLinesMax * (int)sizeof(BoxLine) / 16;
+  const int vp = (bn.visit_count * (int)sizeof(Visit) + 15) / 16;
+  const int lp = (bn.line_count * (int)sizeof(BoxLine) + 15) / 16;
+  const int wbase = tid & ~63;
+  if (wbase < kVisitPieces && tid < vp)
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(visits + bn.visit_first) + 16 * tid,
+                                     lds_ptr(reinterpret_cast<char *>(svis_dst) + 16 * wbase), 16, 0, 0);
+  if (wbase < kLinePieces && tid < lp)
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(lines + bn.line_first) + 16 * tid,
+                                     lds_ptr(reinterpret_cast<char *>(slines_dst) + 16 * wbase), 16, 0, 0);
+}
+
 // Box apply (default scatter).  A box is (part of) one brick of cells: the kernel runs the per-face
 // pipeline of face_kernel over the box's face visits, expanding only into the brick's cells (a face
 // split between two bricks is visited twice, once per half), and sums the results in a dense LDS
@@ -412,6 +430,11 @@ __device__ __forceinline__ void box_body(
   gather_line<T, NN>(x + (box_base + glo), nxp.gofs, nxp.sn, lnext);
   if (VJP) gather_line<T, NN>(u2 + (box_base + glo), nxp.gofs, nxp.sn, unext);
   int buf = 0;
+  // The accumulator is zeroed once here; afterwards each box's flush clears the nodes it read, which
+  // are exactly the nodes its visits added into, so every box starts from zero.
+#pragma unroll
+  for (int i = 0; i < (ACC + kBoxThreads - 1) / kBoxThreads; ++i)
+    if (i * kBoxThreads + tid < ACC) acc[i * kBoxThreads + tid] = A(0);
 
   for (;;) {
     // ---- box `cur`: its visits are in svis[buf], its line records in slines, and the gather of its
@@ -426,9 +449,6 @@ __device__ __forceinline__ void box_body(
     }
     int ticket = 0;  // draws the box after `nxt` (thread 0); settled at the end of this box
     if (tid == 0 && nxt >= 0) ticket = draw_ticket(sched, sg);
-#pragma unroll
-    for (int i = 0; i < (ACC + kBoxThreads - 1) / kBoxThreads; ++i)
-      if (i * kBoxThreads + tid < ACC) acc[i * kBoxThreads + tid] = A(0);
     // Per flush line, one packed word: -1 when the lane's node is not touched, else the box line index
     // (bits 0-7), a shared flag (bit 8) and, for a shared node, its halo slot relative to the box's
     // first (bits 9-21).  All records are read before any is decoded, and the decode has no branches.
@@ -449,25 +469,16 @@ __device__ __forceinline__ void box_body(
     double pj[k];
 #pragma unroll
     for (int j = 0; j < k; ++j) pj[j] = 0.0;
-    __syncthreads();  // acc zeroed before any add; slines read before it is refilled
+    __syncthreads();  // the previous flush cleared acc; slines read before it is refilled
     // Copy the next box's visits and line records straight from global memory into LDS (16 bytes per
     // lane, no registers held); the last batch of this box waits for the copies before its barrier.
-    // The global arrays are padded so that the last 16-byte piece stays inside them.
-    if (nxt >= 0) {
-      constexpr int kVisitPieces = kMaxBoxVisits * (int)sizeof(Visit) / 16;
-      constexpr int kLinePieces = kLinesMax * (int)sizeof(BoxLine) / 16;
-      const int vp = (bn.visit_count * (int)sizeof(Visit) + 15) / 16;
-      const int lp = (bn.line_count * (int)sizeof(BoxLine) + 15) / 16;
-      const int wbase = tid & ~63;
-      if (wbase < kVisitPieces && tid < vp)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(visits + bn.visit_first) + 16 * tid,
-                                         lds_ptr(reinterpret_cast<char *>(&svis[buf ^ 1][0]) + 16 * wbase), 16, 0, 0);
-      if (wbase < kLinePieces && tid < lp)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(lines + bn.line_first) + 16 * tid,
-                                         lds_ptr(reinterpret_cast<char *>(&slines[0]) + 16 * wbase), 16, 0, 0);
-    }
-    T yv[kLines];
+    // The copies are issued after the first batch's contraction (so that the wait for that batch's
+    // gather does not also wait for them), or here when the box has a single batch.  The global arrays
+    // are padded so that the last 16-byte piece stays inside them.
     const int nbat = (bc.visit_count + FPB - 1) / FPB;
+    if (nxt >= 0 && nbat == 1)
+      copy_box_records<kLinesMax>(visits, lines, bn, &svis[buf ^ 1][0], slines, tid);
+    T yv[kLines];
     for (int b = 0; b < nbat; ++b) {
       const VisitPrep cur_p = nxp;
       const bool last = b + 1 == nbat;
@@ -523,6 +534,7 @@ __device__ __forceinline__ void box_body(
         for (int j = 0; j < k; ++j) sa[(f * k + j) * TL + t] = a[j];
       }
       __syncthreads();
+      if (b == 0 && !last && nxt >= 0) copy_box_records<kLinesMax>(visits, lines, bn, &svis[buf ^ 1][0], slines, tid);
       if (last && accumulate) {  // y at the exclusive flush nodes
 #pragma unroll
         for (int m = 0; m < kLines; ++m) {
@@ -641,6 +653,7 @@ __device__ __forceinline__ void box_body(
       if (fl[m] >= 0) {
         const unsigned line = (unsigned)fl[m] & 0xFF;
         A v = acc[gx + P * (int)line];
+        acc[gx + P * (int)line] = A(0);
         if (fl[m] & (1 << 8)) {
           halo[bc.halo_first + (fl[m] >> 9)] = (T)v;
         } else {
@@ -975,6 +988,40 @@ hipError_t launch_set_gamma(const DevPlan &p, const double *gamma_dev, hipStream
 
 hipError_t launch_set_gamma_host(const DevPlan &p, GammaArg g, hipStream_t s) {
   hipLaunchKernelGGL(set_gamma_host_kernel, dim3(1), dim3(128), 0, s, g, p.k, p.tab64, p.tab32);
+  return hipGetLastError();
+}
+
+// diag[node] += the diagonal of G at every patch node of every face: for the patch node at normal
+// position i and tangential positions (t1, t2), sum_j coef_j g_j[i]^2 M[t1][t1] M[t2][t2] (the
+// diagonal of the Kronecker factors, §2.4).  One workgroup per face batch; FP64 atomics (setup-time
+// use by the preconditioned CG).
+__global__ void ghost_diag_kernel(double *__restrict__ diag, const int64_t *__restrict__ face_base,
+                                  const Batch *__restrict__ batches, const double *__restrict__ tab, int dim, int k,
+                                  int s0, int s1, int s2) {
+  const Batch bt = batches[blockIdx.x];
+  const int K = k + 1, NN = 2 * k + 1;
+  const int np = NN * K * (dim == 3 ? K : 1);
+  const double *g = tab, *M = tab + tab_M(k), *coef = tab + tab_coef(k);
+  const int axis = bt.axis;
+  const int sn = axis == 0 ? s0 : (axis == 1 ? s1 : s2);
+  const int st1 = axis == 0 ? s1 : s0;
+  const int st2 = dim == 3 ? (axis == 2 ? s1 : s2) : 0;
+  for (int idx = threadIdx.x; idx < bt.count * np; idx += blockDim.x) {
+    const int f = idx / np, q = idx - f * np;
+    const int i = q % NN, t = q / NN, t1 = t % K, t2 = t / K;
+    double gi = 0.0;
+    for (int j = 0; j < k; ++j) gi += coef[j] * g[j * NN + i] * g[j * NN + i];
+    const double v = gi * M[t1 * K + t1] * (dim == 3 ? M[t2 * K + t2] : 1.0);
+    atomicAdd(&diag[face_base[bt.first + f] + (int64_t)i * sn + (int64_t)t1 * st1 + (int64_t)t2 * st2], v);
+  }
+}
+
+hipError_t launch_zero_support(const DevPlan &p, double *y, hipStream_t s) { return zero_support(p, y, s); }
+
+hipError_t launch_ghost_diag(const DevPlan &p, double *diag, hipStream_t s) {
+  if (p.n_batches == 0) return hipSuccess;
+  hipLaunchKernelGGL(ghost_diag_kernel, dim3(p.n_batches), dim3(kBlockThreads), 0, s, diag, p.face_base, p.batches,
+                     (const double *)p.tab64, p.dim, p.k, p.stride[0], p.stride[1], p.stride[2]);
   return hipGetLastError();
 }
 

@@ -151,14 +151,24 @@ class GhostOperator:
         L.check(self._lib.ghost_set_gamma(self._h, ctypes.cast(arr, ctypes.c_void_p), 0, _stream(self._dev())))
         self.gamma = vals
 
+    def ghost_diag(self, out=None, accumulate=False):
+        """Diagonal of G (FP64, on the support; other entries of a fresh output are 0)."""
+        import torch
+        if out is None:
+            out = torch.zeros(self.n_lattice, dtype=torch.float64, device=self._dev())
+        self._vec(out, torch.float64, "diag")
+        L.check(self._lib.ghost_diag(self._h, _ptr(out), int(accumulate), _stream(self._dev())))
+        return out
+
     def mass_diag(self):
         import torch
         out = torch.empty(self.n_lattice, dtype=torch.float64, device=self._dev())
         L.check(self._lib.ghost_mass_diag(self._h, _ptr(out), _stream(self._dev())))
         return out
 
-    def cg(self, b, x=None, mode="fp64", tol=1e-10, max_iter=20000, inner_tol=1e-4, check_every=50):
-        """Solve (M + G) x = b on the active nodes; returns (x, result dict).  Synchronous."""
+    def cg(self, b, x=None, mode="fp64", tol=1e-10, max_iter=20000, inner_tol=1e-4, check_every=50, precond="none"):
+        """Solve (M + G) x = b on the active nodes; returns (x, result dict).  Synchronous.
+        precond: "none" or "jacobi" (diagonal of M + G)."""
         import torch
         self._vec(b, torch.float64, "b")
         if x is None:
@@ -167,6 +177,7 @@ class GhostOperator:
         opts = L.GhostCgOpts()
         opts.mode = {"fp64": L.GHOST_CG_FP64, "mixed": L.GHOST_CG_MIXED}[mode]
         opts.tol, opts.max_iter, opts.inner_tol, opts.check_every = tol, max_iter, inner_tol, check_every
+        opts.precond = {"none": L.GHOST_CG_NONE, "jacobi": L.GHOST_CG_JACOBI}[precond]
         res = L.GhostCgResult()
         L.check(self._lib.ghost_cg(self._h, _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(res),
                                    _stream(self._dev())))

@@ -124,3 +124,35 @@ def test_cg_small(mode):
     xr, it, rr = cg_reference(A, b[active], tol=1e-10)
     # parity of x beyond the residual is bounded by the conditioning; compare loosely
     assert np.linalg.norm(x[active] - xr) <= 1e-4 * np.linalg.norm(xr)
+
+
+@pytest.mark.parametrize("name", ["disk2d_q2_32", "small_q3_12"])
+def test_ghost_diag_matches_oracle(name):
+    """ghost_diag equals the diagonal of the oracle's assembled G (FP64, 1e-12 normwise), zero off the
+    support in overwrite mode, and adds in accumulate mode."""
+    w = WORKLOADS.get(name) or Workload("small_q3_12", 3, 3, (12,) * 3, (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)
+    o = oracle(w)
+    ref = np.asarray(o.sparse().diagonal())
+    op = gpu_op(w)
+    got = op.ghost_diag().cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    base = torch.ones(w.n_lattice, dtype=torch.float64, device="cuda")
+    acc = op.ghost_diag(base.clone(), accumulate=True).cpu().numpy()
+    assert np.max(np.abs(acc - 1.0 - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_cg_jacobi_small(mode):
+    """Jacobi-preconditioned CG reaches the FP64 true-residual tolerance against the oracle's A."""
+    w = Workload("small_q3_12", 3, 3, (12,) * 3, (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)
+    o = oracle(w)
+    A, active = o.system()
+    b = np.zeros(w.n_lattice)
+    b[active] = uniform_vector(w.n_lattice, SEED_B)[active]
+    op = gpu_op(w)
+    x, res = op.cg(torch.from_numpy(b).cuda(), mode=mode, tol=1e-10, max_iter=20000, precond="jacobi")
+    x = x.cpu().numpy()
+    rel = np.linalg.norm(b[active] - A @ x[active]) / np.linalg.norm(b[active])
+    assert res["converged"] and rel <= 1.5e-10 and abs(rel - res["rel_residual"]) <= 1e-3 * rel + 1e-11
+    _, res_plain = op.cg(torch.from_numpy(b).cuda(), mode=mode, tol=1e-10, max_iter=20000)
+    assert res["iterations"] < res_plain["iterations"]

@@ -214,6 +214,7 @@ def test_host_only_context_refuses_device_work(lib):
     assert lib.ghost_vjp(op._h, p, p, q, q, 0, None) == L.GHOST_ESTATE
     assert lib.ghost_mass_diag(op._h, p, None) == L.GHOST_ESTATE
     assert lib.ghost_set_gamma(op._h, p, 0, None) == L.GHOST_ESTATE
+    assert lib.ghost_diag(op._h, p, 0, None) == L.GHOST_ESTATE
     assert lib.ghost_set_timing(op._h, 1) == L.GHOST_ESTATE
     assert lib.ghost_kernel_times(op._h, None, None, None) == L.GHOST_ESTATE
     assert lib.ghost_set_timing(None, 1) == L.GHOST_EINVAL
