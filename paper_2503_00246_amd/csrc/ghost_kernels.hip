@@ -715,15 +715,23 @@ __global__ __launch_bounds__(kBoxThreads) void box_kernel_wide(GHOST_BOX_PARAMS)
 #undef GHOST_BOX_PARAMS
 #undef GHOST_BOX_ARGS
 
-// y[node] (+)= sum of the node's halo slots, for every support node on a shared box face.
+// y[node] (+)= sum of the node's halo slots, for every node more than one box touches.  The first
+// n_pairs nodes have exactly two slots, at 2h and 2h + 1: their loads do not wait on a pointer.
 template <typename T>
 __global__ void halo_kernel(T *__restrict__ y, const T *__restrict__ halo, const int64_t *__restrict__ node,
-                            const int32_t *__restrict__ ptr, const int32_t *__restrict__ slot, int n, int accumulate) {
+                            const int32_t *__restrict__ ptr, const int32_t *__restrict__ slot, int n, int n_pairs,
+                            int accumulate) {
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= n) return;
-  T s = T(0);
-  for (int q = ptr[h]; q < ptr[h + 1]; ++q) s += halo[slot[q]];
   T *p = y + node[h];
+  T s;
+  if (h < n_pairs) {
+    const int2 q = reinterpret_cast<const int2 *>(slot)[h];
+    s = halo[q.x] + halo[q.y];
+  } else {
+    s = T(0);
+    for (int q = ptr[h]; q < ptr[h + 1]; ++q) s += halo[slot[q]];
+  }
   *p = accumulate ? *p + s : s;
 }
 
@@ -901,7 +909,8 @@ hipError_t dispatch_box(const DevPlan &p, const T *x, const T *u2, T *y, const T
   if (e != hipSuccess) return e;
   if (p.n_halo > 0) {
     hipLaunchKernelGGL((halo_kernel<T>), dim3((p.n_halo + kBlockThreads - 1) / kBlockThreads), dim3(kBlockThreads),
-                       0, s, y, (const T *)halo, p.halo_node, p.halo_ptr, p.halo_slot, p.n_halo, (int)accumulate);
+                       0, s, y, (const T *)halo, p.halo_node, p.halo_ptr, p.halo_slot, p.n_halo, p.n_halo_pairs,
+                       (int)accumulate);
     e = hipGetLastError();
   }
   mark(p, 2, s);

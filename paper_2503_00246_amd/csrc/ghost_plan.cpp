@@ -633,17 +633,26 @@ std::string build_box_layout(Plan &p) {
   std::sort(halo.begin(), halo.end(), [](const HaloRef &x, const HaloRef &y) {
     return x.node != y.node ? x.node < y.node : x.slot < y.slot;
   });
+  // Halo CSR: the nodes with exactly two slots first (most shared nodes lie on one face between two
+  // boxes; their slots sit at 2h, 2h+1 and the pass needs no pointer), then the others, each group in
+  // ascending node order.
   p.halo_node.clear();
   p.halo_ptr.clear();
   p.halo_slot.clear();
-  for (size_t i = 0; i < halo.size(); ++i) {
-    if (i == 0 || halo[i].node != halo[i - 1].node) {
-      p.halo_node.push_back(halo[i].node);
+  std::vector<std::pair<size_t, size_t>> groups;  // [begin, end) in `halo` per node
+  for (size_t i = 0; i < halo.size(); ++i)
+    if (i == 0 || halo[i].node != halo[i - 1].node) groups.push_back({i, i});
+  for (size_t g = 0; g < groups.size(); ++g) groups[g].second = g + 1 < groups.size() ? groups[g + 1].first : halo.size();
+  for (int pass = 0; pass < 2; ++pass)
+    for (const auto &g : groups) {
+      if ((g.second - g.first == 2) != (pass == 0)) continue;
+      p.halo_node.push_back(halo[g.first].node);
       p.halo_ptr.push_back((int32_t)p.halo_slot.size());
+      for (size_t i = g.first; i < g.second; ++i) p.halo_slot.push_back(halo[i].slot);
     }
-    p.halo_slot.push_back(halo[i].slot);
-  }
   p.halo_ptr.push_back((int32_t)p.halo_slot.size());
+  p.n_halo_pairs = 0;
+  for (const auto &g : groups) p.n_halo_pairs += g.second - g.first == 2 ? 1 : 0;
   return "";
 }
 

@@ -92,7 +92,9 @@ struct Plan {
   std::vector<BoxLine> box_lines;      // device form
   int64_t n_visits = 0;
   int64_t n_slots = 0;                 // halo slots
-  std::vector<int64_t> halo_node;      // shared support nodes (lattice index), ascending
+  std::vector<int64_t> halo_node;      // shared support nodes (lattice index): the n_halo_pairs nodes
+                                       // with two slots, then the others, each group ascending
+  int64_t n_halo_pairs = 0;
   std::vector<int32_t> halo_ptr;       // slots of halo_node[h]: halo_slot[halo_ptr[h] .. halo_ptr[h+1])
   std::vector<int32_t> halo_slot;
 
