@@ -180,10 +180,11 @@ def test_kernel_timing_records_every_call(scatter):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_apply_128_k5_on_face_subset(precision):
-    """ball3d_q5_128 at full size, in the benchmark's launch configuration: compare y at every node of a
-    seeded 1% face sample's patches, with the oracle summing all faces touching those nodes."""
-    w = WORKLOADS["ball3d_q5_128"]
+@pytest.mark.parametrize("name", ["ball3d_q5_128", "ball3d_q7_96"])
+def test_apply_full_size_on_face_subset(name, precision):
+    """Full-size meshes (128^3 Q5 and 96^3 Q7), in the benchmark's launch configuration: compare y at every
+    node of a seeded 1% face sample's patches, with the oracle summing all faces touching those nodes."""
+    w = WORKLOADS[name]
     op = gpu_op(w)
     o = oracle_for(w)
     faces_all = np.concatenate([np.c_[np.full(len(o.faces[a]), a), o.faces[a]] for a in range(3)])
@@ -206,3 +207,20 @@ def test_apply_128_k5_on_face_subset(precision):
         ref = o.apply_at(u32.astype(np.float64), dofs)
         y = op.apply_f32(torch.from_numpy(u32).cuda())[torch.from_numpy(dofs).cuda()].cpu().numpy()
         assert nerr(y.astype(np.float64), ref) <= TOL32
+
+
+def test_apply_split_boxes():
+    """k = 1 on 20 x 19 x 18 cells: bricks of 15^3 cells hold more face visits than one box, so they are
+    split into several boxes over the same node box, whose common nodes all go through the halo pass."""
+    w = Workload("split_q1", 3, 1, (20, 19, 18), (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)
+    op = gpu_op(w)
+    boxes, _, _ = op.box_layout()
+    assert len(np.unique(boxes[:, :3], axis=0)) < len(boxes)
+    o = GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), centre=w.centre, radius=w.radius)
+    u = uniform_vector(w.n_lattice, SEED_U)
+    ref, sup = o.apply(u), o.support()
+    ut = torch.from_numpy(u).cuda()
+    assert nerr(op.apply(ut).cpu().numpy()[sup], ref[sup]) <= TOL64
+    y0 = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U + 10)).cuda()
+    ya = op.apply(ut, y0.clone(), accumulate=True).cpu().numpy()
+    assert nerr(ya - y0.cpu().numpy(), ref) <= TOL64
