@@ -32,6 +32,7 @@ constexpr int lines_per_face(int dim, int k) { return dim == 3 ? (k + 1) * (k + 
 
 // Faces handled by one workgroup of kBlockThreads threads, and per batch of the box kernel.
 constexpr int faces_per_block(int dim, int k) { return kBlockThreads / lines_per_face(dim, k); }
-constexpr int box_faces_per_batch(int dim, int k) { return kBoxThreads / lines_per_face(dim, k); }
+// box kernel: a face never straddles a wavefront, 64 / lines faces per wave
+constexpr int box_faces_per_batch(int dim, int k) { return (kBoxThreads / 64) * (64 / lines_per_face(dim, k)); }
 
 }  // namespace ghost

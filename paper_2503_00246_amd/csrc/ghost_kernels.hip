@@ -333,6 +333,13 @@ __device__ __forceinline__ BoxScalars load_box(const Box *__restrict__ boxes, in
   return r;
 }
 
+// Orders a wave's LDS writes before its later reads by other lanes of the same wave (LDS executes a
+// wave's instructions in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Copy a box's visits and line records from global memory into LDS in 16-byte pieces, one per lane,
 // without holding them in registers (waves past the last piece issue nothing).
 template <int kLinesMax>
@@ -357,9 +364,12 @@ __device__ __forceinline__ void copy_box_records(const Visit *__restrict__ visit
 // accumulator over the brick's node box (odd row pitch, so the lanes of a face spread over the banks).
 // Nodes that no other box touches are then written to y with plain stores; the others go to halo
 // slots that halo_kernel adds into y.  No global atomics on y, and y needs no prior zeroing.
+// A face's tangential lines never straddle a wavefront (64 / (k+1)^(d-1) faces per wave), so the
+// mass passes exchange values through the wave's own LDS rows without workgroup barriers: each wave
+// works through its faces of the box independently, and the workgroup meets once per box.
 // The workgroups are persistent: each takes boxes from the scheduler and, while it works on one box,
-// already loads the next box's visits and line records and issues the gather of its first batch, so
-// that only the first box of a workgroup waits on memory before computing.
+// already loads the next box's visits and line records; the gather of the next box's first faces is
+// issued before the flush of this one.
 // VJP: x = w drives du; u2 = u gives the order-wise reduction, counted on each face's primary visit,
 // and stored per box so that the reduction order does not depend on the schedule.
 template <typename T, int D, int K, bool VJP>
@@ -369,7 +379,9 @@ __device__ __forceinline__ void box_body(
     const BoxLine *__restrict__ lines, const T *__restrict__ tab, int s1, int s2, int accumulate, int n_boxes,
     BoxSched *__restrict__ sched) {
   constexpr int k = K - 1, NN = 2 * k + 1;
-  constexpr int TL = lines_per_face(D, k), FPB = kBoxThreads / TL, NT = TL * FPB;
+  // faces never straddle a wavefront: FW faces per wave, FPB per batch over the workgroup
+  constexpr int TL = lines_per_face(D, k), FW = 64 / TL, FPB = box_faces_per_batch(D, k);
+  static_assert(TL <= 64, "a face must fit one wavefront");
   constexpr int E = box_extent(D), P = box_pitch(D), ACC = box_acc(D);
   constexpr int kLinesMax = D == 3 ? E * E : E;
   // jump vectors and mass matrix as compile-time constants (folded into the instructions); only the
@@ -396,8 +408,9 @@ __device__ __forceinline__ void box_body(
   const int lo = (int)((int64_t)n_boxes * sg / ng), hi = (int)((int64_t)n_boxes * (sg + 1) / ng);
 
   // per-thread constants: face slot and tangential line of the face pipeline, flush lane group
-  const int f = tid / TL, t = tid - f * TL;
-  const bool in_block = tid < NT;
+  const int lane_w = tid & 63, fw = lane_w / TL;
+  const int f = (tid >> 6) * FW + fw, t = lane_w - fw * TL;
+  const bool in_block = fw < FW;
   const int t1 = (D == 3) ? t % K : t;
   const int t2 = (D == 3) ? t / K : 0;
   // Flush plan: a group of E lanes takes touched x-lines grp, grp + kGroups, ... of the box, lane = box
@@ -475,8 +488,11 @@ __device__ __forceinline__ void box_body(
     // The copies are issued after the first batch's contraction (so that the wait for that batch's
     // gather does not also wait for them), or here when the box has a single batch.  The global arrays
     // are padded so that the last 16-byte piece stays inside them.
-    const int nbat = (bc.visit_count + FPB - 1) / FPB;
-    if (nxt >= 0 && nbat == 1)
+    // Each wave works through its own faces of the box (round b: visit b * FPB + f) and stops after
+    // its last; no workgroup barrier is needed until the box is done.
+    const int wave_first = (tid >> 6) * FW;
+    const int nbat = bc.visit_count > wave_first ? (bc.visit_count - wave_first + FPB - 1) / FPB : 0;
+    if (nxt >= 0 && nbat <= 1)
       copy_box_records<kLinesMax>(visits, lines, bn, &svis[buf ^ 1][0], slines, tid);
     T yv[kLines];
     for (int b = 0; b < nbat; ++b) {
@@ -488,8 +504,6 @@ __device__ __forceinline__ void box_body(
         line[i] = lnext[i];
         uline[i] = VJP ? unext[i] : T(0);
       }
-      // the copies of the next box's records land before the barrier that precedes their use
-      if (last) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
 
       // normal contraction a_j = g_j . line, folded with the reflection symmetry g_j[2k-i] = (-1)^(j+1)
       // g_j[i] (derivative order j+1 odd for even j here: those rows use the sums, the others the
@@ -533,7 +547,7 @@ __device__ __forceinline__ void box_body(
 #pragma unroll
         for (int j = 0; j < k; ++j) sa[(f * k + j) * TL + t] = a[j];
       }
-      __syncthreads();
+      wave_sync();
       if (b == 0 && !last && nxt >= 0) copy_box_records<kLinesMax>(visits, lines, bn, &svis[buf ^ 1][0], slines, tid);
       if (last && accumulate) {  // y at the exclusive flush nodes
 #pragma unroll
@@ -543,8 +557,9 @@ __device__ __forceinline__ void box_body(
           yv[m] = yb[excl ? (uint32_t)(gx + s1 * (int)(line % E) + s2 * (int)(line / E)) : 0u];
         }
       }
-      // issue the next gather: the next batch of this box, or the first batch of the next box
-      if (!last || nxt >= 0) {
+      // issue the next gather: the next batch of this box (the next box's first batch is gathered after
+      // the barrier that ends this box)
+      if (!last) {
         const int vi = last ? f : (b + 1) * FPB + f;
         const int nv = last ? bn.visit_count : bc.visit_count;
         const bool live = in_block && vi < nv;
@@ -571,7 +586,7 @@ __device__ __forceinline__ void box_body(
             row[q] = s;
           }
         }
-        __syncthreads();
+        wave_sync();
         if (in_block && t2 < k) {
           T *col = &sa[(f * k + t2) * TL + t1];
           T r[K];
@@ -585,7 +600,7 @@ __device__ __forceinline__ void box_body(
             col[q * K] = s;
           }
         }
-        __syncthreads();
+        wave_sync();
       } else {
         if (in_block && t < k) {
           T *row = &sa[(f * k + t) * TL];
@@ -600,7 +615,7 @@ __device__ __forceinline__ void box_body(
             row[q] = s;
           }
         }
-        __syncthreads();
+        wave_sync();
       }
       T cj[k];
 #pragma unroll
@@ -644,7 +659,26 @@ __device__ __forceinline__ void box_body(
           for (int j = 0; j < k; ++j) pj[j] += (double)au[j] * (double)cj[j];
         }
       }
-      __syncthreads();  // sa is reused by the next batch, acc is complete after the last
+      wave_sync();  // sa is reused by this wave's next batch
+    }
+    if (nbat == 0 && accumulate) {  // a wave without faces in this box still flushes its lines
+#pragma unroll
+      for (int m = 0; m < kLines; ++m) {
+        const unsigned line = (unsigned)fl[m] & 0xFF;
+        const bool excl = fl[m] >= 0 && !(fl[m] & (1 << 8));
+        yv[m] = yb[excl ? (uint32_t)(gx + s1 * (int)(line % E) + s2 * (int)(line / E)) : 0u];
+      }
+    }
+    // all waves done with this box: acc complete; the next box's records (copied by every wave, each
+    // waiting for its own copies) visible; then its first gather overlaps the flush
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    if (nxt >= 0) {
+      const bool live = in_block && f < bn.visit_count;
+      const Visit v = live ? svis[buf ^ 1][f] : Visit(0);
+      nxp = prep_visit<D, K>(v, live, t1, t2, s1, s2, bn.o0, bn.o1, bn.o2, nglo);
+      gather_line<T, NN>(x + (nbase + nglo), nxp.gofs, nxp.sn, lnext);
+      if (VJP) gather_line<T, NN>(u2 + (nbase + nglo), nxp.gofs, nxp.sn, unext);
     }
 
     // flush: exclusive nodes to y, shared ones to their halo slot
