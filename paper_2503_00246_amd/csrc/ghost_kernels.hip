@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlockThreads) void face_kernel(
 struct VisitPrep {
   uint32_t gofs;   // offset (elements) of the thread's normal line, patch plane 0, from the gather base
   uint32_t sn;     // lattice stride along the normal (0 for dead lanes: they read the gather base)
-  int acc0, dacc;  // FP64 accumulator byte offset of the line at patch plane 0, byte stride along the normal
+  int acc0, dacc;  // accumulator index of the line at patch plane 0, index stride along the normal
   bool lo, hi;     // expand patch planes 0..k / k+1..2k
   bool live, prim;
 };
@@ -243,8 +243,8 @@ __device__ __forceinline__ VisitPrep prep_visit(Visit vis, bool live, int t1, in
   q.prim = half != 2;
   q.gofs = live ? (uint32_t)(bx + s1 * by + s2 * bz - glo) : 0u;
   q.sn = live ? (uint32_t)(axis == 0 ? 1 : (axis == 1 ? s1 : s2)) : 0u;
-  q.acc0 = (int)sizeof(double) * (bx + P * (by + E * bz));
-  q.dacc = (int)sizeof(double) * (axis == 0 ? 1 : (axis == 1 ? P : P * E));
+  q.acc0 = bx + P * (by + E * bz);
+  q.dacc = axis == 0 ? 1 : (axis == 1 ? P : P * E);
   q.lo = half != 2;
   q.hi = half != 1;
   return q;
@@ -315,6 +315,25 @@ __device__ __forceinline__ int gather_low(int o0, int o1, int o2, int k, int s1,
   return -(int)(base < reach ? base : reach);
 }
 
+// A visit record of the current box, read from LDS.  The next box's records may be on their way into
+// the other half of the same array by LDS DMA, and the compiler, unable to tell the two halves apart,
+// would make this read wait for every global load the wave has in flight (the next gather among them).
+// The read is written out with its own wait instead; its address never meets the DMA's.
+__device__ __forceinline__ Visit read_visit(const Visit *p) {
+  Visit v;
+  const uint32_t a = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const Visit *)p;
+  asm volatile("ds_read_b64 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(a) : "memory");
+  return v;
+}
+
+// Accumulator add in LDS, without return.  Written out for the same reason as read_visit: the compiler
+// cannot tell the accumulator from the destination of the records' LDS DMA either.  (LDS operations of
+// one wave complete in order, and every barrier waits for all of them.)
+__device__ __forceinline__ void acc_add(double *p, double v) {
+  const uint32_t a = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) double *)p;
+  asm volatile("ds_add_f64 %0, %1" : : "v"(a), "v"(v) : "memory");
+}
+
 // Box fields as wave-uniform scalars.
 struct BoxScalars {
   int o0, o1, o2, visit_first, visit_count, line_first, line_count, halo_first;
@@ -340,8 +359,19 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads also waits for every global load and
+// store the wave has in flight; the box kernel's waves never read each other's global stores, and its
+// gathers are meant to stay in flight across the barriers between boxes.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Copy a box's visits and line records from global memory into LDS in 16-byte pieces, one per lane,
-// without holding them in registers (waves past the last piece issue nothing).
+// without holding them in registers (waves past the last piece issue nothing).  Addresses are a uniform
+// base plus a 32-bit lane offset (the record arrays are far below 4 GB), so no 64-bit per-lane pointer
+// stays live across the box.
 template <int kLinesMax>
 __device__ __forceinline__ void copy_box_records(const Visit *__restrict__ visits, const BoxLine *__restrict__ lines,
                                                  const BoxScalars &bn, Visit *svis_dst, BoxLine *slines_dst, int tid) {
@@ -349,13 +379,37 @@ __device__ __forceinline__ void copy_box_records(const Visit *__restrict__ visit
   constexpr int kLinePieces = kLinesMax * (int)sizeof(BoxLine) / 16;
   const int vp = (bn.visit_count * (int)sizeof(Visit) + 15) / 16;
   const int lp = (bn.line_count * (int)sizeof(BoxLine) + 15) / 16;
-  const int wbase = tid & ~63;
+  const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // wave-uniform: the LDS base goes to M0
+  const uint32_t lane_ofs = 16u * (uint32_t)tid;
   if (wbase < kVisitPieces && tid < vp)
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(visits + bn.visit_first) + 16 * tid,
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(visits) +
+                                         ((uint32_t)bn.visit_first * (uint32_t)sizeof(Visit) + lane_ofs),
                                      lds_ptr(reinterpret_cast<char *>(svis_dst) + 16 * wbase), 16, 0, 0);
   if (wbase < kLinePieces && tid < lp)
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(lines + bn.line_first) + 16 * tid,
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(lines) +
+                                         ((uint32_t)bn.line_first * (uint32_t)sizeof(BoxLine) + lane_ofs),
                                      lds_ptr(reinterpret_cast<char *>(slines_dst) + 16 * wbase), 16, 0, 0);
+}
+
+// Flush plan of a box, one packed word per flush line of the lane: -1 when the lane's node is not
+// touched, else the box line index (bits 0-7), a shared flag (bit 8) and, for a shared node, its halo
+// slot relative to the box's first (bits 9-21).  All records are read before any is decoded, and the
+// decode has no branches.
+template <int D, int kLines, int kGroups>
+__device__ __forceinline__ void decode_lines(const BoxLine *slines, int grp, LineMask<D> gbit, int line_count,
+                                             int halo_first, int (&fl)[kLines]) {
+  using Mask = LineMask<D>;
+  BoxLine bl[kLines];
+#pragma unroll
+  for (int m = 0; m < kLines; ++m) bl[m] = slines[grp + m * kGroups];
+#pragma unroll
+  for (int m = 0; m < kLines; ++m) {
+    const Mask tm = (Mask)bl[m].touched, sm = (Mask)bl[m].shared;
+    const bool touched = grp + m * kGroups < line_count && (tm & gbit) != 0;
+    const bool sh = (sm & gbit) != 0;
+    const int rel = bl[m].slot_base - halo_first + popc_mask(sm & (gbit - 1));
+    fl[m] = touched ? (bl[m].line | (sh ? (1 << 8) | (rel << 9) : 0)) : -1;
+  }
 }
 
 // Box apply (default scatter).  A box is (part of) one brick of cells: the kernel runs the per-face
@@ -399,7 +453,6 @@ __device__ __forceinline__ void box_body(
   __shared__ Visit svis[2][kMaxBoxVisits];  // visits of the current box and of the next one
   __shared__ BoxLine slines[kLinesMax];     // line records of the current box, then of the next one
   __shared__ int s_box[2];
-  char *const accb = reinterpret_cast<char *>(acc);
   const int tid = threadIdx.x;
 
   // scheduling group and its box range
@@ -443,11 +496,16 @@ __device__ __forceinline__ void box_body(
   gather_line<T, NN>(x + (box_base + glo), nxp.gofs, nxp.sn, lnext);
   if (VJP) gather_line<T, NN>(u2 + (box_base + glo), nxp.gofs, nxp.sn, unext);
   int buf = 0;
+  int fl[kLines];
+  decode_lines<D, kLines, kGroups>(slines, grp, gbit, bc.line_count, bc.halo_first, fl);
   // The accumulator is zeroed once here; afterwards each box's flush clears the nodes it read, which
   // are exactly the nodes its visits added into, so every box starts from zero.
 #pragma unroll
   for (int i = 0; i < (ACC + kBoxThreads - 1) / kBoxThreads; ++i)
     if (i * kBoxThreads + tid < ACC) acc[i * kBoxThreads + tid] = A(0);
+  // acc zeroed and the first box's line records decoded before any wave adds into acc or copies the
+  // next box's records over them
+  lds_barrier();
 
   for (;;) {
     // ---- box `cur`: its visits are in svis[buf], its line records in slines, and the gather of its
@@ -462,35 +520,20 @@ __device__ __forceinline__ void box_body(
     }
     int ticket = 0;  // draws the box after `nxt` (thread 0); settled at the end of this box
     if (tid == 0 && nxt >= 0) ticket = draw_ticket(sched, sg);
-    // Per flush line, one packed word: -1 when the lane's node is not touched, else the box line index
-    // (bits 0-7), a shared flag (bit 8) and, for a shared node, its halo slot relative to the box's
-    // first (bits 9-21).  All records are read before any is decoded, and the decode has no branches.
-    int fl[kLines];
-    {
-      BoxLine bl[kLines];
-#pragma unroll
-      for (int m = 0; m < kLines; ++m) bl[m] = slines[grp + m * kGroups];
-#pragma unroll
-      for (int m = 0; m < kLines; ++m) {
-        const Mask tm = (Mask)bl[m].touched, sm = (Mask)bl[m].shared;
-        const bool touched = grp + m * kGroups < bc.line_count && (tm & gbit) != 0;
-        const bool sh = (sm & gbit) != 0;
-        const int rel = bl[m].slot_base - bc.halo_first + popc_mask(sm & (gbit - 1));
-        fl[m] = touched ? (bl[m].line | (sh ? (1 << 8) | (rel << 9) : 0)) : -1;
-      }
-    }
+    // (the flush plan fl of this box was decoded before the barrier that ended the previous box, which
+    // also ordered the previous flush's clearing of acc before this box's adds)
     double pj[k];
 #pragma unroll
     for (int j = 0; j < k; ++j) pj[j] = 0.0;
-    __syncthreads();  // the previous flush cleared acc; slines read before it is refilled
     // Copy the next box's visits and line records straight from global memory into LDS (16 bytes per
-    // lane, no registers held); the last batch of this box waits for the copies before its barrier.
-    // The copies are issued after the first batch's contraction (so that the wait for that batch's
-    // gather does not also wait for them), or here when the box has a single batch.  The global arrays
-    // are padded so that the last 16-byte piece stays inside them.
+    // lane, no registers held); each wave waits for its copies before the barrier that ends the box.
+    // A wave issues them in its first round, behind the gather of its second (so that no wait for a
+    // gather also waits for them), or here when it has at most one round.  The global arrays are
+    // padded so that the last 16-byte piece stays inside them.
     // Each wave works through its own faces of the box (round b: visit b * FPB + f) and stops after
-    // its last; no workgroup barrier is needed until the box is done.
-    const int wave_first = (tid >> 6) * FW;
+    // its last; no workgroup barrier is needed until the box is done.  (The round count is
+    // wave-uniform, made visible as such to the compiler so that the round's branches are scalar.)
+    const int wave_first = __builtin_amdgcn_readfirstlane((tid >> 6) * FW);
     const int nbat = bc.visit_count > wave_first ? (bc.visit_count - wave_first + FPB - 1) / FPB : 0;
     if (nxt >= 0 && nbat <= 1)
       copy_box_records<kLinesMax>(visits, lines, bn, &svis[buf ^ 1][0], slines, tid);
@@ -498,6 +541,10 @@ __device__ __forceinline__ void box_body(
     for (int b = 0; b < nbat; ++b) {
       const VisitPrep cur_p = nxp;
       const bool last = b + 1 == nbat;
+      // the next round's visit record, read before this round's contraction waits for its gather
+      const int vi = (b + 1) * FPB + f;
+      const bool vlive = !last && in_block && vi < bc.visit_count;
+      const Visit vrec = vlive ? read_visit(&svis[buf][vi]) : Visit(0);
       T line[NN], uline[NN];
 #pragma unroll
       for (int i = 0; i < NN; ++i) {
@@ -548,7 +595,6 @@ __device__ __forceinline__ void box_body(
         for (int j = 0; j < k; ++j) sa[(f * k + j) * TL + t] = a[j];
       }
       wave_sync();
-      if (b == 0 && !last && nxt >= 0) copy_box_records<kLinesMax>(visits, lines, bn, &svis[buf ^ 1][0], slines, tid);
       if (last && accumulate) {  // y at the exclusive flush nodes
 #pragma unroll
         for (int m = 0; m < kLines; ++m) {
@@ -560,15 +606,10 @@ __device__ __forceinline__ void box_body(
       // issue the next gather: the next batch of this box (the next box's first batch is gathered after
       // the barrier that ends this box)
       if (!last) {
-        const int vi = last ? f : (b + 1) * FPB + f;
-        const int nv = last ? bn.visit_count : bc.visit_count;
-        const bool live = in_block && vi < nv;
-        const Visit v = live ? svis[last ? buf ^ 1 : buf][vi] : Visit(0);
-        const int64_t gb = last ? nbase + nglo : box_base + glo;
-        nxp = last ? prep_visit<D, K>(v, live, t1, t2, s1, s2, bn.o0, bn.o1, bn.o2, nglo)
-                   : prep_visit<D, K>(v, live, t1, t2, s1, s2, bc.o0, bc.o1, bc.o2, glo);
-        gather_line<T, NN>(x + gb, nxp.gofs, nxp.sn, lnext);
-        if (VJP) gather_line<T, NN>(u2 + gb, nxp.gofs, nxp.sn, unext);
+        nxp = prep_visit<D, K>(vrec, vlive, t1, t2, s1, s2, bc.o0, bc.o1, bc.o2, glo);
+        gather_line<T, NN>(x + (box_base + glo), nxp.gofs, nxp.sn, lnext);
+        if (VJP) gather_line<T, NN>(u2 + (box_base + glo), nxp.gofs, nxp.sn, unext);
+        if (b == 0 && nxt >= 0) copy_box_records<kLinesMax>(visits, lines, bn, &svis[buf ^ 1][0], slines, tid);
       }
       // tangential masses in place: each row (column) is read and rewritten by the one thread that owns
       // it, and the barrier between the passes orders the row writes before the column reads
@@ -644,15 +685,13 @@ __device__ __forceinline__ void box_body(
           int off = cur_p.acc0;
 #pragma unroll
           for (int i = 0; i <= k; ++i, off += cur_p.dacc)
-            __hip_atomic_fetch_add(reinterpret_cast<A *>(accb + off), (A)yv2[i], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            acc_add(&acc[off], (A)yv2[i]);
         }
         if (cur_p.hi) {
           int off = cur_p.acc0 + (k + 1) * cur_p.dacc;
 #pragma unroll
           for (int i = k + 1; i < NN; ++i, off += cur_p.dacc)
-            __hip_atomic_fetch_add(reinterpret_cast<A *>(accb + off), (A)yv2[i], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            acc_add(&acc[off], (A)yv2[i]);
         }
         if (VJP && cur_p.prim) {
 #pragma unroll
@@ -670,9 +709,12 @@ __device__ __forceinline__ void box_body(
       }
     }
     // all waves done with this box: acc complete; the next box's records (copied by every wave, each
-    // waiting for its own copies) visible; then its first gather overlaps the flush
+    // waiting for its own copies) visible; then its first gather overlaps the flush.  The ticket drawn
+    // at the top of the box has returned too: thread 0 publishes the box after `nxt` now, so that no
+    // wave waits for its flush stores at the barrier that ends the box.
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-    __syncthreads();
+    lds_barrier();
+    if (tid == 0) s_box[0] = nxt >= 0 ? settle_ticket(sched, sg, ticket, lo, hi, nblk) : -1;
     if (nxt >= 0) {
       const bool live = in_block && f < bn.visit_count;
       const Visit v = live ? svis[buf ^ 1][f] : Visit(0);
@@ -681,13 +723,22 @@ __device__ __forceinline__ void box_body(
       if (VJP) gather_line<T, NN>(u2 + (nbase + nglo), nxp.gofs, nxp.sn, unext);
     }
 
-    // flush: exclusive nodes to y, shared ones to their halo slot
+    // flush: exclusive nodes to y, shared ones to their halo slot.  Every lane first reads and clears its
+    // accumulator slots (a lane without a node on a line uses the pad column of row 0, which no face adds
+    // into), so that the reads are issued together; then the stores follow.
+    int ai[kLines];
+    A av[kLines];
+#pragma unroll
+    for (int m = 0; m < kLines; ++m) ai[m] = fl[m] >= 0 ? gx + P * (int)((unsigned)fl[m] & 0xFF) : E;
+#pragma unroll
+    for (int m = 0; m < kLines; ++m) av[m] = acc[ai[m]];
+#pragma unroll
+    for (int m = 0; m < kLines; ++m) acc[ai[m]] = A(0);
 #pragma unroll
     for (int m = 0; m < kLines; ++m) {
       if (fl[m] >= 0) {
         const unsigned line = (unsigned)fl[m] & 0xFF;
-        A v = acc[gx + P * (int)line];
-        acc[gx + P * (int)line] = A(0);
+        A v = av[m];
         if (fl[m] & (1 << 8)) {
           halo[bc.halo_first + (fl[m] >> 9)] = (T)v;
         } else {
@@ -706,7 +757,7 @@ __device__ __forceinline__ void box_body(
         for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
         if (lane == 0) red[wave][j] = v;
       }
-      __syncthreads();
+      lds_barrier();
       if (tid < k) {
         double sum = 0.0;
 #pragma unroll
@@ -714,8 +765,11 @@ __device__ __forceinline__ void box_body(
         partial[(int64_t)cur * k + tid] = sum;
       }
     }
-    if (tid == 0) s_box[0] = nxt >= 0 ? settle_ticket(sched, sg, ticket, lo, hi, nblk) : -1;
-    __syncthreads();  // acc read by the flush before the next zeroing; s_box published
+    // the next box's flush plan, from its line records (in LDS since the barrier that ended this box)
+    if (nxt >= 0) decode_lines<D, kLines, kGroups>(slines, grp, gbit, bn.line_count, bn.halo_first, fl);
+    // acc read and cleared by the flush before the next box adds into it; slines decoded before the
+    // next box's copies refill it; s_box published
+    lds_barrier();
     if (nxt < 0) break;
     cur = nxt;
     bc = bn;
@@ -734,8 +788,9 @@ __device__ __forceinline__ void box_body(
 #define GHOST_BOX_ARGS x, u2, y, halo, partial, boxes, visits, lines, tab, s1, s2, accumulate, n_boxes, sched
 
 // Two blocks of 512 threads per CU need at most 128 VGPRs (4 waves per SIMD); the compiler is held to
-// that where it fits without spilling (the apply up to k = 6).  The VJP and k = 7 carry more live
-// values and run one block per CU instead.
+// that for the apply (FP32 at every degree and FP64 up to k = 6 fit without spilling).  The VJP and the
+// FP64 apply at k = 7 carry more live values and run one block per CU instead: spilled values reloaded
+// behind a gather would make the flush wait for it.
 template <typename T, int D, int K, bool VJP>
 __global__ __launch_bounds__(kBoxThreads) __attribute__((amdgpu_waves_per_eu(4))) void box_kernel(
     GHOST_BOX_PARAMS) {
@@ -894,7 +949,9 @@ void launch_box(const DevPlan &p, const T *x, const T *u2, T *y, T *halo, const 
                 hipStream_t s) {
   // persistent workgroups: as many as fit on the device at once (the first launch asks the runtime)
   const void *fn;
-  if constexpr (VJP)
+  // the VJP and the FP64 apply at k = 7 hold too many live values for 128 VGPRs: one block per CU
+  constexpr bool kWide = VJP || (sizeof(T) == 8 && K == 8);
+  if constexpr (kWide)
     fn = reinterpret_cast<const void *>(&box_kernel_wide<T, D, K, VJP>);
   else
     fn = reinterpret_cast<const void *>(&box_kernel<T, D, K, VJP>);
@@ -906,7 +963,7 @@ void launch_box(const DevPlan &p, const T *x, const T *u2, T *y, T *halo, const 
   }
   const int resident = per_cu * (p.n_cu > 0 ? p.n_cu : 1);
   const dim3 grid(p.n_boxes < resident ? p.n_boxes : resident), block(kBoxThreads);
-  if constexpr (VJP)
+  if constexpr (kWide)
     hipLaunchKernelGGL((box_kernel_wide<T, D, K, VJP>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes,
                        p.visits, p.box_lines, tab, p.stride[1], p.stride[2], (int)accumulate, p.n_boxes, p.sched);
   else
