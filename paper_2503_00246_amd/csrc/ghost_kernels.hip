@@ -433,7 +433,7 @@ __device__ __forceinline__ void box_body(
     const BoxLine *__restrict__ lines, const T *__restrict__ tab, int s1, int s2, int accumulate, int n_boxes,
     BoxSched *__restrict__ sched) {
   constexpr int k = K - 1, NN = 2 * k + 1;
-  // faces never straddle a wavefront: FW faces per wave, FPB per batch over the workgroup
+  // faces never straddle a wavefront: FW faces per wave, FPB per round over the workgroup
   constexpr int TL = lines_per_face(D, k), FW = 64 / TL, FPB = box_faces_per_batch(D, k);
   static_assert(TL <= 64, "a face must fit one wavefront");
   constexpr int E = box_extent(D), P = box_pitch(D), ACC = box_acc(D);
@@ -509,7 +509,7 @@ __device__ __forceinline__ void box_body(
 
   for (;;) {
     // ---- box `cur`: its visits are in svis[buf], its line records in slines, and the gather of its
-    // first batch is in flight in lnext / unext
+    // first round is in flight in lnext / unext
     T *const yb = y + box_base;
     BoxScalars bn{};
     int64_t nbase = 0;
@@ -603,7 +603,7 @@ __device__ __forceinline__ void box_body(
           yv[m] = yb[excl ? (uint32_t)(gx + s1 * (int)(line % E) + s2 * (int)(line / E)) : 0u];
         }
       }
-      // issue the next gather: the next batch of this box (the next box's first batch is gathered after
+      // issue the next gather: the next round of this box (the next box's first round is gathered after
       // the barrier that ends this box)
       if (!last) {
         nxp = prep_visit<D, K>(vrec, vlive, t1, t2, s1, s2, bc.o0, bc.o1, bc.o2, glo);
@@ -698,7 +698,7 @@ __device__ __forceinline__ void box_body(
           for (int j = 0; j < k; ++j) pj[j] += (double)au[j] * (double)cj[j];
         }
       }
-      wave_sync();  // sa is reused by this wave's next batch
+      wave_sync();  // sa is reused by this wave's next round
     }
     if (nbat == 0 && accumulate) {  // a wave without faces in this box still flushes its lines
 #pragma unroll
