@@ -213,7 +213,7 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
               : (flags & GHOST_ATOMIC) ? ghost::Scatter::Atomic : ghost::Scatter::Box;
   d.n_boxes = (int)p.boxes.size();
   d.n_halo = (int)p.halo_node.size();
-  d.n_halo_pairs = (int)p.n_halo_pairs;
+  d.n_halo_single = (int)p.n_halo_single;
   d.coloured = p.coloured;
   d.n_colours = p.n_colours;
   d.colour_begin = p.colour_begin.empty() ? nullptr : p.colour_begin.data();

@@ -63,7 +63,7 @@ struct DevPlan {
   const int32_t *halo_ptr = nullptr;
   const int32_t *halo_slot = nullptr;
   int n_halo = 0;
-  int n_halo_pairs = 0;               // halo_node[0, n_halo_pairs) have slots halo_slot[2h], [2h + 1]
+  int n_halo_single = 0;              // halo_node[0, n_halo_single) have the one slot halo_slot[h]
   BoxSched *sched = nullptr;          // zero-initialised at setup
   int n_cu = 0;                       // compute units of the device
   // optional timing events: recorded before the scatter kernels, between them and the halo pass,

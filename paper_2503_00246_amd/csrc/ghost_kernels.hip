@@ -416,8 +416,9 @@ __device__ __forceinline__ void decode_lines(const BoxLine *slines, int grp, Lin
 // pipeline of face_kernel over the box's face visits, expanding only into the brick's cells (a face
 // split between two bricks is visited twice, once per half), and sums the results in a dense LDS
 // accumulator over the brick's node box (odd row pitch, so the lanes of a face spread over the banks).
-// Nodes that no other box touches are then written to y with plain stores; the others go to halo
-// slots that halo_kernel adds into y.  No global atomics on y, and y needs no prior zeroing.
+// Every node is then written to y with a plain store by the first box (in box order) that touches it;
+// later boxes touching it store their part into halo slots, which halo_kernel adds into y.  No global
+// atomics on y, and y needs no prior zeroing.
 // A face's tangential lines never straddle a wavefront (64 / (k+1)^(d-1) faces per wave), so the
 // mass passes exchange values through the wave's own LDS rows without workgroup barriers: each wave
 // works through its faces of the box independently, and the workgroup meets once per box.
@@ -804,24 +805,24 @@ __global__ __launch_bounds__(kBoxThreads) void box_kernel_wide(GHOST_BOX_PARAMS)
 #undef GHOST_BOX_PARAMS
 #undef GHOST_BOX_ARGS
 
-// y[node] (+)= sum of the node's halo slots, for every node more than one box touches.  The first
-// n_pairs nodes have exactly two slots, at 2h and 2h + 1: their loads do not wait on a pointer.
+// y[node] += sum of the node's halo slots, for every node more than one box touches (the first box to
+// touch it has already written y there, in either mode).  The first n_single nodes have one slot, at
+// slot[h]: their loads do not wait on a pointer.
 template <typename T>
 __global__ void halo_kernel(T *__restrict__ y, const T *__restrict__ halo, const int64_t *__restrict__ node,
-                            const int32_t *__restrict__ ptr, const int32_t *__restrict__ slot, int n, int n_pairs,
-                            int accumulate) {
+                            const int32_t *__restrict__ ptr, const int32_t *__restrict__ slot, int n,
+                            int n_single) {
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= n) return;
   T *p = y + node[h];
   T s;
-  if (h < n_pairs) {
-    const int2 q = reinterpret_cast<const int2 *>(slot)[h];
-    s = halo[q.x] + halo[q.y];
+  if (h < n_single) {
+    s = halo[slot[h]];
   } else {
     s = T(0);
     for (int q = ptr[h]; q < ptr[h + 1]; ++q) s += halo[slot[q]];
   }
-  *p = accumulate ? *p + s : s;
+  *p += s;
 }
 
 template <typename T>
@@ -1000,8 +1001,7 @@ hipError_t dispatch_box(const DevPlan &p, const T *x, const T *u2, T *y, const T
   if (e != hipSuccess) return e;
   if (p.n_halo > 0) {
     hipLaunchKernelGGL((halo_kernel<T>), dim3((p.n_halo + kBlockThreads - 1) / kBlockThreads), dim3(kBlockThreads),
-                       0, s, y, (const T *)halo, p.halo_node, p.halo_ptr, p.halo_slot, p.n_halo, p.n_halo_pairs,
-                       (int)accumulate);
+                       0, s, y, (const T *)halo, p.halo_node, p.halo_ptr, p.halo_slot, p.n_halo, p.n_halo_single);
     e = hipGetLastError();
   }
   mark(p, 2, s);

@@ -515,9 +515,9 @@ std::string build_box_layout(Plan &p) {
       tmp.push_back(std::move(t));
     }
   }
-  // Touched nodes of each box (union over its visits of the expanded part of the patch), and how
-  // many boxes touch each support node: a node touched by one box is written by that box, the
-  // others go through halo slots.
+  // Touched nodes of each box (union over its visits of the expanded part of the patch).  The first box
+  // (in box order) that touches a support node writes it to y; every later box touching it sends its
+  // contribution through a halo slot, which the halo pass adds to y.
   std::vector<int64_t> sup_start(p.support_runs.size()), sup_off(p.support_runs.size());
   {
     int64_t acc = 0;
@@ -531,7 +531,6 @@ std::string build_box_layout(Plan &p) {
     const size_t r = (size_t)(std::upper_bound(sup_start.begin(), sup_start.end(), node) - sup_start.begin()) - 1;
     return sup_off[r] + (node - sup_start[r]);
   };
-  std::vector<uint8_t> touches((size_t)p.n_support, 0);
   for (BoxTmp &t : tmp) {
     std::vector<Interval> iv;
     for (Visit v : t.v) {
@@ -549,12 +548,8 @@ std::string build_box_layout(Plan &p) {
     }
     int64_t tot = 0;
     merge_runs(iv, p.L[0], t.runs, tot);
-    for (const Run &r : t.runs) {
-      const int64_t base = sup_index(r.start);
-      for (int64_t q = 0; q < r.len; ++q)
-        if (touches[base + q] < 255) ++touches[base + q];
-    }
   }
+  std::vector<uint8_t> claimed((size_t)p.n_support, 0);  // a box already writes the node to y
 
   struct HaloRef { int64_t node; int32_t slot; };
   std::vector<HaloRef> halo;
@@ -586,12 +581,13 @@ std::string build_box_layout(Plan &p) {
       const int64_t Y = line % p.L[1], Z = line / p.L[1];
       const int64_t ry = d >= 2 ? Y - bx.org[1] : 0, rz = d >= 3 ? Z - bx.org[2] : 0;
       const int64_t sbase = sup_index(r.start);
-      // split the run where the shared status changes
+      // split the run where the status changes: written to y by this box, or through a halo slot
       int64_t q0 = 0;
       while (q0 < r.len) {
-        const bool node_shared = touches[sbase + q0] > 1;
+        const bool node_shared = claimed[sbase + q0] != 0;
         int64_t q1 = q0 + 1;
-        while (q1 < r.len && (touches[sbase + q1] > 1) == node_shared) ++q1;
+        while (q1 < r.len && (claimed[sbase + q1] != 0) == node_shared) ++q1;
+        for (int64_t q = q0; q < q1; ++q) claimed[sbase + q] = 1;
         const int64_t rx = x0 + q0 - bx.org[0];
         BoxRun br{};
         br.start = r.start + q0;
@@ -633,8 +629,8 @@ std::string build_box_layout(Plan &p) {
   std::sort(halo.begin(), halo.end(), [](const HaloRef &x, const HaloRef &y) {
     return x.node != y.node ? x.node < y.node : x.slot < y.slot;
   });
-  // Halo CSR: the nodes with exactly two slots first (most shared nodes lie on one face between two
-  // boxes; their slots sit at 2h, 2h+1 and the pass needs no pointer), then the others, each group in
+  // Halo CSR: the nodes with exactly one slot first (most shared nodes lie on one face between two
+  // boxes; the pass reads their slot at h without the pointer), then the others, each group in
   // ascending node order.
   p.halo_node.clear();
   p.halo_ptr.clear();
@@ -645,14 +641,14 @@ std::string build_box_layout(Plan &p) {
   for (size_t g = 0; g < groups.size(); ++g) groups[g].second = g + 1 < groups.size() ? groups[g + 1].first : halo.size();
   for (int pass = 0; pass < 2; ++pass)
     for (const auto &g : groups) {
-      if ((g.second - g.first == 2) != (pass == 0)) continue;
+      if ((g.second - g.first == 1) != (pass == 0)) continue;
       p.halo_node.push_back(halo[g.first].node);
       p.halo_ptr.push_back((int32_t)p.halo_slot.size());
       for (size_t i = g.first; i < g.second; ++i) p.halo_slot.push_back(halo[i].slot);
     }
   p.halo_ptr.push_back((int32_t)p.halo_slot.size());
-  p.n_halo_pairs = 0;
-  for (const auto &g : groups) p.n_halo_pairs += g.second - g.first == 2 ? 1 : 0;
+  p.n_halo_single = 0;
+  for (const auto &g : groups) p.n_halo_single += g.second - g.first == 1 ? 1 : 0;
   return "";
 }
 

@@ -27,9 +27,9 @@ struct Run {            // maximal run of consecutive lattice nodes along x
 // Box scatter: the cells are cut into bricks of B^d cells.  A workgroup handles one brick: it applies
 // every face with a cell in the brick (a face whose two cells lie in different bricks is visited by
 // both, each expanding only into its own cell; the shared node plane goes to the lower cell's brick),
-// sums the contributions over the brick's node box [org, org + kB] in a dense LDS accumulator, writes
-// nodes that no other box contains straight to y, and stores nodes on shared box faces into halo
-// slots, which a second kernel adds into y.
+// sums the contributions over the brick's node box [org, org + kB] in a dense LDS accumulator and
+// writes its nodes straight to y, except nodes on box faces that an earlier box (in box order) also
+// touches: those go into halo slots, which a second kernel adds into y.
 struct Box {
   int32_t org[3];         // node origin k*B*b (0 for unused axes)
   int32_t visit_first, visit_count;
@@ -39,8 +39,8 @@ struct Box {
 };
 
 // One touched x-line of a box node box: bit x of `touched` marks box node x of the line as a node the
-// box contributes to; bit x of `shared` marks it as a node another box touches too
-// (its value goes to halo slot slot_base + (number of shared bits below x) instead of y).
+// box contributes to; bit x of `shared` marks it as a node an earlier box (in box order) already writes
+// to y (this box's value goes to halo slot slot_base + (number of shared bits below x) instead).
 struct BoxLine {
   uint64_t touched, shared;
   int32_t line;        // ry + E * rz (box-relative line coordinates, E = box_extent)
@@ -92,9 +92,9 @@ struct Plan {
   std::vector<BoxLine> box_lines;      // device form
   int64_t n_visits = 0;
   int64_t n_slots = 0;                 // halo slots
-  std::vector<int64_t> halo_node;      // shared support nodes (lattice index): the n_halo_pairs nodes
-                                       // with two slots, then the others, each group ascending
-  int64_t n_halo_pairs = 0;
+  std::vector<int64_t> halo_node;      // support nodes with halo slots (lattice index): the n_halo_single
+                                       // nodes with one slot, then the others, each group ascending
+  int64_t n_halo_single = 0;
   std::vector<int32_t> halo_ptr;       // slots of halo_node[h]: halo_slot[halo_ptr[h] .. halo_ptr[h+1])
   std::vector<int32_t> halo_slot;
 

@@ -211,7 +211,8 @@ def test_apply_full_size_on_face_subset(name, precision):
 
 def test_apply_split_boxes():
     """k = 1 on 20 x 19 x 18 cells: bricks of 15^3 cells hold more face visits than one box, so they are
-    split into several boxes over the same node box, whose common nodes all go through the halo pass."""
+    split into several boxes over the same node box: the first of them writes their common nodes to y,
+    the others add theirs through the halo pass."""
     w = Workload("split_q1", 3, 1, (20, 19, 18), (-1.0,) * 3, (0.011, 0.017, 0.023), 0.73)
     op = gpu_op(w)
     boxes, _, _ = op.box_layout()
