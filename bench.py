@@ -82,7 +82,9 @@ def cpu_baseline(w, u_np, budget_s=10.0):
     """
     from threadpoolctl import threadpool_info
     from oracle.operator import GhostOracle
+    t_setup = time.perf_counter()
     o = GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), centre=w.centre, radius=w.radius)
+    t_setup = time.perf_counter() - t_setup
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     reps, t0 = 0, time.perf_counter()
     while True:
@@ -94,8 +96,19 @@ def cpu_baseline(w, u_np, budget_s=10.0):
     faces = o.n_faces()
     return {"value": round(reps * faces * w.n_p / dt / 1e9, 6), "unit": "GDoF/s", "cores": threads, "kind": "oracle",
             "sample": f"{reps} full oracle applies of {w.name} ({faces} faces each: dense per-face patch matvec "
-                      f"by BLAS + scatter-add) in {dt:.1f} s; host {platform.processor() or platform.machine()}, "
-                      f"{os.cpu_count()} logical CPUs, BLAS threads {threads}"}
+                      f"by BLAS + scatter-add) in {dt:.1f} s (oracle set-up, timed apart: {t_setup:.1f} s); host "
+                      f"{cpu_model()}, {os.cpu_count()} logical CPUs, BLAS threads {threads}"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def run_workload(w, args, with_cpu):
@@ -124,6 +137,9 @@ def run_workload(w, args, with_cpu):
     t64, box64, halo64 = timed(lambda: op.apply(u, y, accumulate=True))
     patch_dofs = st["n_faces_total"] * st["n_patch_dofs"]
     out = {"t64": t64, "box64": box64, "halo64": halo64, "gdofs64": patch_dofs / t64 / 1e9, "stats": st}
+    if not args.sweep:
+        t64o, _, _ = timed(lambda: op.apply(u, y, accumulate=False))
+        out["t64_overwrite"] = t64o
     if not args.no_fp32:
         u32 = u.float()
         y32 = torch.zeros_like(u32)
@@ -271,6 +287,11 @@ def main():
                      "traffic": traffic, "bytes_per_launch": box_bytes(st, 8),
                      "avg_launch_us": round(r["box64"] * 1e6, 2), "halo_pass_us": round(r["halo64"] * 1e6, 2)},
         "apply_roofline_frac": round(st["bytes_fp64"] / r["t64"] / 1e9 / HBM_PEAK_GBS, 4),
+        # faces x patch DoFs x 24 B per apply time: the traffic the per-face patches would move without
+        # any reuse between overlapping patches
+        "patch_traffic_GBps": round(r["gdofs64"] * 24, 1),
+        "overwrite": {"ms_per_step": round(r["t64_overwrite"] * 1e3, 5),
+                      "value": round(st["n_faces_total"] * st["n_patch_dofs"] / r["t64_overwrite"] / 1e9, 4)},
         "fp32": None if "t32" not in r else {
             "value": round(r["gdofs32"], 4), "unit": "GDoF/s", "ms_per_step": round(r["t32"] * 1e3, 5),
             "normwise_err_vs_fp64": r["err32"],
