@@ -11,12 +11,14 @@ normwise error against the FP64 result.
 Prints ONE JSON line.  Metric: ghost-face patch DoFs per second,
 faces * (2k+1)(k+1)^{d-1} / t / 1e9.  The roofline object refers to the box
 kernel (the dominant kernel of an apply; the halo pass that follows it adds
-the contributions of nodes shared between boxes): its algorithmic HBM bytes
-per launch (read u on the support, read and write y on the nodes it owns:
-8 B per support DoF + 16 B per exclusive DoF in FP64) over its average launch
-duration, measured with HIP events that the library records on the apply's
-stream around each kernel during the timed steps.  apply_roofline_frac gives
-the same ratio for the whole apply: 24 B per support DoF over the step time.
+the other boxes' parts at nodes shared between boxes): its algorithmic HBM
+bytes per launch (read u, read and write y on the support: 24 B per support
+DoF in FP64) over its average launch duration, measured with HIP events that
+the library records on the apply's stream around each kernel during a second
+pass of the same length (the headline step time comes from a pass without
+them).  apply_roofline_frac gives the same ratio for the whole apply.  Extra
+fields: the overwrite mode, and the applies captured in a HIP graph and
+replayed (no launch gaps).
 """
 
 import argparse
@@ -111,6 +113,35 @@ def cpu_model():
     return platform.processor() or platform.machine()
 
 
+def graph_time(fn, steps, repeats=10):
+    """Seconds per apply from HIP events around a graph of `steps` captured applies: the median of
+    `repeats` replays (no launch gaps between the applies)."""
+    import statistics
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(steps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(repeats):
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        g.replay()
+        end.record()
+        torch.cuda.synchronize()
+        times.append(start.elapsed_time(end) / 1e3 / steps)
+    del g
+    return statistics.median(times)
+
+
 def run_workload(w, args, with_cpu):
     import numpy as np
     import torch
@@ -124,12 +155,15 @@ def run_workload(w, args, with_cpu):
     y = torch.zeros_like(u)
 
     def timed(fn):
+        # the applies are timed without the library's per-kernel events (which add work of their own);
+        # a second pass of the same length records them, for the box kernel's and the halo pass's times
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
-        op.kernel_times()  # drop anything recorded before the timed steps
-        op.set_timing(True)
         t = timed_applies(fn, args.steps, 0)
+        op.kernel_times()  # drop anything recorded before
+        op.set_timing(True)
+        timed_applies(fn, args.steps, 0)
         op.set_timing(False)
         kt = op.kernel_times()
         return t, kt["main_ms"] / 1e3 / kt["calls"], kt["halo_ms"] / 1e3 / kt["calls"]
@@ -140,6 +174,7 @@ def run_workload(w, args, with_cpu):
     if not args.sweep:
         t64o, _, _ = timed(lambda: op.apply(u, y, accumulate=False))
         out["t64_overwrite"] = t64o
+        out["t64_graph"] = graph_time(lambda: op.apply(u, y, accumulate=True), args.steps)
     if not args.no_fp32:
         u32 = u.float()
         y32 = torch.zeros_like(u32)
@@ -176,9 +211,10 @@ def run_vjp(w, args):
     for _ in range(args.warmup):
         fn()
     torch.cuda.synchronize()
+    t = timed_applies(fn, args.steps, 0)  # without the per-kernel events; a second pass records them
     op.kernel_times()
     op.set_timing(True)
-    t = timed_applies(fn, args.steps, 0)
+    timed_applies(fn, args.steps, 0)
     op.set_timing(False)
     kt = op.kernel_times()
     box_t = kt["main_ms"] / 1e3 / kt["calls"]
@@ -292,6 +328,9 @@ def main():
         "patch_traffic_GBps": round(r["gdofs64"] * 24, 1),
         "overwrite": {"ms_per_step": round(r["t64_overwrite"] * 1e3, 5),
                       "value": round(st["n_faces_total"] * st["n_patch_dofs"] / r["t64_overwrite"] / 1e9, 4)},
+        "graph": {"ms_per_step": round(r["t64_graph"] * 1e3, 5),
+                  "value": round(st["n_faces_total"] * st["n_patch_dofs"] / r["t64_graph"] / 1e9, 4),
+                  "timing": f"median of 10 replays of a graph of {args.steps} captured applies"},
         "fp32": None if "t32" not in r else {
             "value": round(r["gdofs32"], 4), "unit": "GDoF/s", "ms_per_step": round(r["t32"] * 1e3, 5),
             "normwise_err_vs_fp64": r["err32"],

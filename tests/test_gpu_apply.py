@@ -225,3 +225,44 @@ def test_apply_split_boxes():
     y0 = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U + 10)).cuda()
     ya = op.apply(ut, y0.clone(), accumulate=True).cpu().numpy()
     assert nerr(ya - y0.cpu().numpy(), ref) <= TOL64
+
+
+def test_apply_graph_replay():
+    """The apply allocates nothing and never waits on the host, so a stream capture of it replays: an
+    FP64 overwrite and an FP32 accumulating apply captured in one HIP graph, replayed three times with
+    eager work and synchronisation between the replays, each replay against the eager result (the LDS
+    sums of the box kernel may add in another order, hence the normwise bars)."""
+    w = WORKLOADS["ball3d_q3_64"]
+    op = gpu_op(w)
+    o = oracle_for(w)
+    sup = torch.from_numpy(o.support()).cuda()
+    u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda()
+    u32 = u.float()
+    ref = op.apply(u)
+    ref32 = op.apply_f32(u32).double()
+    y = torch.zeros_like(u)
+    y32 = torch.zeros_like(u32)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream
+        op.apply(u, y)
+        op.apply_f32(u32, y32, accumulate=True)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        op.apply(u, y, accumulate=False)
+        op.apply_f32(u32, y32, accumulate=True)
+    for _ in range(3):
+        y.fill_(7.0)
+        y32.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got, got32 = y.cpu().numpy(), y32.double().cpu().numpy() - 7.0
+        r, r32, s = ref.cpu().numpy(), ref32.cpu().numpy(), sup.cpu().numpy()
+        assert nerr(got[s], r[s]) <= TOL64
+        off = np.ones(w.n_lattice, dtype=bool)
+        off[s] = False
+        assert np.all(got[off] == 7.0)
+        assert nerr(got32[s], r32[s]) <= TOL32
