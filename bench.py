@@ -52,9 +52,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="one JSON line per degree/mesh of the roofline sweep")
-    ap.add_argument("--mode", default="apply", choices=["apply", "vjp", "cg"],
+    ap.add_argument("--mode", default="apply", choices=["apply", "vjp", "cg", "balls"],
                     help="apply: the benchmark line; vjp: ghost_vjp on ball3d_q4_96; cg: FP64 vs mixed CG on "
-                         "ball3d_q7_96 (extra lines, not the benchmark metric)")
+                         "ball3d_q7_96; balls: the multiple-ball problem, throughput against the cut fraction "
+                         "(extra lines, not the benchmark metric)")
+    ap.add_argument("--balls-k", type=int, default=3, help="degree of the multiple-ball problem")
+    ap.add_argument("--balls-n", type=int, default=128, help="cells per axis of the multiple-ball problem")
     ap.add_argument("--cg-max-iter", type=int, default=5000)
     ap.add_argument("--traffic", default=TRAFFIC_FILE, help="JSON file with measured HBM bytes per launch")
     return ap.parse_args()
@@ -254,6 +257,24 @@ def run_cg(w, args):
         print(json.dumps(out), flush=True)
 
 
+def run_balls(args):
+    """The multiple-ball problem: one line per ball count, with the cut fraction of the active cells."""
+    from paper_2503_00246_amd.workloads import multiball_workload
+    args.sweep = True  # one line per workload: no overwrite or graph timings
+    for nb in (1, 2, 4, 8, 16, 32, 64):
+        w = multiball_workload(args.balls_k, args.balls_n, nb)
+        r = run_workload(w, args, with_cpu=False)
+        st = r["stats"]
+        print(json.dumps({"metric": "ghost-face patch DoFs/s (GDoF/s), multiple-ball problem", "workload": w.name,
+                          "balls": nb, "radius": w.radius, "active_cells": st["n_active_cells"],
+                          "cut_cells": st["n_cut_cells"], "cut_fraction": st["n_cut_cells"] / max(1, st["n_active_cells"]),
+                          "faces": st["n_faces_total"], "support_dofs": st["n_support_dofs"],
+                          "ms64": r["t64"] * 1e3, "gdofs64": r["gdofs64"], "box_ms64": r["box64"] * 1e3,
+                          "box_frac64": box_bytes(st, 8) / r["box64"] / 1e9 / HBM_PEAK_GBS,
+                          "ms32": r.get("t32", 0) * 1e3, "gdofs32": r.get("gdofs32"), "err32": r.get("err32")}),
+              flush=True)
+
+
 def box_bytes(st, elem):
     """Algorithmic bytes of one accumulating box-kernel launch: u on the support, and y read and written
     on the support (every support node is written to y by exactly one box, the first that touches it;
@@ -275,6 +296,9 @@ def main():
         return
     if args.mode == "cg":
         run_cg(WORKLOADS["ball3d_q7_96" if args.workload == "ball3d_q5_128" else args.workload], args)
+        return
+    if args.mode == "balls":
+        run_balls(args)
         return
     if args.sweep:
         for k, n in [(3, 128), (3, 96), (4, 96), (5, 96), (5, 128), (6, 96), (7, 96)]:

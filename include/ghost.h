@@ -53,6 +53,7 @@ extern "C" {
 /* level-set kinds */
 #define GHOST_LS_BALL 0  /* phi = radius - |x - centre| (> 0 inside, §2) */
 #define GHOST_LS_CELLS 1 /* caller-provided cell classes */
+#define GHOST_LS_BALLS 2 /* union of balls, phi = max_i (r_i - |x - c_i|) (the multiple-ball problem, §3) */
 
 /* cell classes */
 #define GHOST_OUTSIDE 0
@@ -79,11 +80,18 @@ typedef struct {
   double h;      /* cell side (> 0, finite); cells are squares / cubes (§2) */
 } ghost_mesh;
 
+/* Cell classes from a level set.  Ball: a cell is active when it meets the open ball and inside when
+ * it lies in the closed ball (exact distances; cut = active and not inside).  Union of balls: active
+ * when it meets some open ball, inside when it lies in some closed ball, cut otherwise when active (a
+ * cell that only the union of several balls covers counts as cut). */
 typedef struct {
-  int kind;                      /* GHOST_LS_BALL or GHOST_LS_CELLS */
+  int kind;                      /* GHOST_LS_BALL, GHOST_LS_CELLS or GHOST_LS_BALLS */
   double centre[3];              /* ball only */
   double radius;                 /* ball only, > 0 */
   const signed char *cell_class; /* cells only: HOST array of n0*n1(*n2) classes, x fastest */
+  int n_balls;                   /* balls only: >= 1 */
+  const double *balls;           /* balls only: HOST array of n_balls x (c0, c1, c2, r), c2 ignored in 2D,
+                                    r > 0; read during ghost_setup only */
 } ghost_levelset;
 
 typedef struct {

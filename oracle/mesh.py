@@ -62,6 +62,31 @@ def classify_ball(n, lo, h, centre, radius, min_margin=1e-12):
     return cls
 
 
+def classify_balls(n, lo, h, balls, min_margin=1e-12):
+    """Cell classes for the union of balls (c0, c1, c2, r), the multiple-ball problem of §3.
+
+    A cell is active when it meets some open ball and inside when it lies in some closed ball; an
+    active cell that no single ball contains is cut, also where several balls cover it together (a
+    reading: the paper classifies cells by the level set's sign pattern, which it does not spell out).
+    Raises on a distance within min_margin of some r^2, as classify_ball does.
+    """
+    d = len(n)
+    active = np.zeros(tuple(n), dtype=bool)
+    inside = np.zeros(tuple(n), dtype=bool)
+    for b in balls:
+        dmin2, dmax2 = cell_distances(n, lo, h, tuple(b[:d]))
+        r2 = b[3] * b[3]
+        margin = min(np.min(np.abs(dmin2 - r2)), np.min(np.abs(dmax2 - r2)))
+        if margin <= min_margin:
+            raise ValueError(f"cell classification tie: margin {margin:g}")
+        active |= dmin2 < r2
+        inside |= dmax2 <= r2
+    cls = np.full(tuple(n), OUTSIDE, dtype=np.int8)
+    cls[active] = CUT
+    cls[inside] = INSIDE
+    return cls
+
+
 def classify_ball_loop(n, lo, h, centre, radius):
     """Same classification with a plain loop over cells (brute-force check of classify_ball)."""
     d = len(n)

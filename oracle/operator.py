@@ -25,13 +25,15 @@ from .basis import gll_weights
 
 
 class GhostOracle:
-    """Ghost-penalty operator on a Cartesian mesh with a ball (or given cell classes)."""
+    """Ghost-penalty operator on a Cartesian mesh with a ball, a union of balls, or given cell classes."""
 
     def __init__(self, d, n, lo, h, k, gamma, centre=None, radius=None, cell_class=None,
-                 per_face=False, check_faces=8, seed=0):
+                 per_face=False, check_faces=8, seed=0, balls=None):
         self.d, self.n, self.lo, self.h, self.k = d, tuple(n), tuple(lo), float(h), k
         self.gamma = np.asarray(gamma, dtype=np.float64)
-        if cell_class is None:
+        if balls:
+            self.cls = mesh.classify_balls(self.n, self.lo, self.h, balls)
+        elif cell_class is None:
             self.cls = mesh.classify_ball(self.n, self.lo, self.h, centre, radius)
         else:
             self.cls = np.asarray(cell_class, dtype=np.int8).reshape(self.n, order="F")

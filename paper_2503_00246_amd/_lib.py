@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libghost.so
 
 GHOST_OK, GHOST_EINVAL, GHOST_ENOMEM, GHOST_EHIP, GHOST_ESTATE = 0, -1, -2, -3, -4
 GHOST_KMAX = 7
-GHOST_LS_BALL, GHOST_LS_CELLS = 0, 1
+GHOST_LS_BALL, GHOST_LS_CELLS, GHOST_LS_BALLS = 0, 1, 2
 GHOST_FP64, GHOST_FP32, GHOST_COLOURED, GHOST_ATOMIC = 1, 2, 4, 8
 GHOST_CG_FP64, GHOST_CG_MIXED = 0, 1
 GHOST_CG_NONE, GHOST_CG_JACOBI = 0, 1
@@ -28,7 +28,8 @@ class GhostMesh(ctypes.Structure):
 
 class GhostLevelset(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("centre", ctypes.c_double * 3), ("radius", ctypes.c_double),
-                ("cell_class", ctypes.POINTER(ctypes.c_byte))]
+                ("cell_class", ctypes.POINTER(ctypes.c_byte)), ("n_balls", ctypes.c_int),
+                ("balls", ctypes.POINTER(ctypes.c_double))]
 
 
 class GhostStats(ctypes.Structure):

@@ -172,6 +172,14 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
       if (!std::isfinite(ls->centre[a])) return fail(GHOST_EINVAL, "centre must be finite");
   } else if (ls->kind == GHOST_LS_CELLS) {
     if (!ls->cell_class) return fail(GHOST_EINVAL, "cell_class is null");
+  } else if (ls->kind == GHOST_LS_BALLS) {
+    if (ls->n_balls < 1 || !ls->balls) return fail(GHOST_EINVAL, "balls: need n_balls >= 1 and a ball array");
+    for (int i = 0; i < ls->n_balls; ++i) {
+      const double *b = ls->balls + 4 * i;
+      for (int a = 0; a < mesh->dim; ++a)
+        if (!std::isfinite(b[a])) return fail(GHOST_EINVAL, "ball %d: centre must be finite", i);
+      if (!(b[3] > 0) || !std::isfinite(b[3])) return fail(GHOST_EINVAL, "ball %d: radius must be positive", i);
+    }
   } else {
     return fail(GHOST_EINVAL, "unknown level-set kind %d", ls->kind);
   }
@@ -185,7 +193,8 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
   try {
     c->gamma.assign(gamma, gamma + k);
     std::string err = ghost::build_plan(c->plan, mesh->dim, mesh->n, mesh->lo, mesh->h, k, ls->kind,
-                                        ls->centre, ls->radius, ls->cell_class, (flags & GHOST_COLOURED) != 0);
+                                        ls->centre, ls->radius, ls->cell_class, ls->n_balls, ls->balls,
+                                        (flags & GHOST_COLOURED) != 0);
     if (!err.empty()) {
       delete c;
       return fail(GHOST_EINVAL, "%s", err.c_str());

@@ -233,7 +233,7 @@ void tables_1d(int k, std::vector<ld> &nodes, std::vector<ld> &weights, std::vec
 
 std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], double h, int k,
                        int ls_kind, const double centre[3], double radius,
-                       const signed char *cell_class, bool coloured) {
+                       const signed char *cell_class, int n_balls, const double *balls, bool coloured) {
   p = Plan();
   p.dim = dim;
   p.k = k;
@@ -262,27 +262,44 @@ std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], dou
       p.cls[i] = (int8_t)v;
     }
   } else {
-    const double r2 = radius * radius;
-    for (int c2 = 0; c2 < p.n[2]; ++c2)
-      for (int c1 = 0; c1 < p.n[1]; ++c1)
-        for (int c0 = 0; c0 < p.n[0]; ++c0) {
-          int c[3] = {c0, c1, c2};
-          double dmin2 = 0.0, dmax2 = 0.0;
-          for (int a = 0; a < dim; ++a) {
-            double cd = (double)c[a];
-            double lo_a = p.lo[a] + cd * h;
-            double hi_a = p.lo[a] + (cd + 1.0) * h;
-            double below = std::max(lo_a - centre[a], 0.0);
-            double above = std::max(centre[a] - hi_a, 0.0);
-            double nearv = std::max(below, above);
-            double farv = std::max(std::fabs(lo_a - centre[a]), std::fabs(hi_a - centre[a]));
-            dmin2 = dmin2 + nearv * nearv;
-            dmax2 = dmax2 + farv * farv;
+    // ball, or union of balls: a cell is INSIDE when some closed ball contains it, CUT when it meets
+    // some open ball without that, OUTSIDE otherwise (exact squared distances of the cell box to the
+    // centre).  Each ball only visits the cells of its bounding box.
+    std::vector<double> one;
+    if (ls_kind == 0) one = {centre[0], centre[1], centre[2], radius};
+    const double *bl = ls_kind == 0 ? one.data() : balls;
+    const int nb = ls_kind == 0 ? 1 : n_balls;
+    for (int i = 0; i < nb; ++i) {
+      const double *b = bl + 4 * i;
+      const double r2 = b[3] * b[3];
+      int cmin[3] = {0, 0, 0}, cmax[3] = {0, 0, 0};
+      for (int a = 0; a < 3; ++a) {
+        if (a >= dim) continue;
+        const double f0 = std::floor((b[a] - b[3] - p.lo[a]) / h) - 1.0, f1 = std::floor((b[a] + b[3] - p.lo[a]) / h) + 1.0;
+        cmin[a] = (int)std::max(0.0, std::min(f0, (double)p.n[a]));
+        cmax[a] = (int)std::max(-1.0, std::min(f1, (double)p.n[a] - 1.0));
+      }
+      for (int c2 = cmin[2]; c2 <= cmax[2]; ++c2)
+        for (int c1 = cmin[1]; c1 <= cmax[1]; ++c1)
+          for (int c0 = cmin[0]; c0 <= cmax[0]; ++c0) {
+            int c[3] = {c0, c1, c2};
+            double dmin2 = 0.0, dmax2 = 0.0;
+            for (int a = 0; a < dim; ++a) {
+              double cd = (double)c[a];
+              double lo_a = p.lo[a] + cd * h;
+              double hi_a = p.lo[a] + (cd + 1.0) * h;
+              double below = std::max(lo_a - b[a], 0.0);
+              double above = std::max(b[a] - hi_a, 0.0);
+              double nearv = std::max(below, above);
+              double farv = std::max(std::fabs(lo_a - b[a]), std::fabs(hi_a - b[a]));
+              dmin2 = dmin2 + nearv * nearv;
+              dmax2 = dmax2 + farv * farv;
+            }
+            int8_t &v = p.cls[c0 + (int64_t)p.n[0] * (c1 + (int64_t)p.n[1] * c2)];
+            if (dmin2 < r2 && dmax2 <= r2) v = GHOST_INSIDE;
+            else if (dmin2 < r2 && v == GHOST_OUTSIDE) v = GHOST_CUT;
           }
-          int8_t v = GHOST_OUTSIDE;
-          if (dmin2 < r2) v = dmax2 <= r2 ? GHOST_INSIDE : GHOST_CUT;
-          p.cls[c0 + (int64_t)p.n[0] * (c1 + (int64_t)p.n[1] * c2)] = v;
-        }
+    }
   }
   for (int8_t v : p.cls) {
     p.n_active_cells += v != GHOST_OUTSIDE;

@@ -113,7 +113,7 @@ struct Plan {
 // Builds the plan; returns an empty string on success or an error message.
 std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], double h, int k,
                        int ls_kind, const double centre[3], double radius,
-                       const signed char *cell_class, bool coloured);
+                       const signed char *cell_class, int n_balls, const double *balls, bool coloured);
 
 // Box layout (see Box).  Called by build_plan.
 std::string build_box_layout(Plan &p);

@@ -24,15 +24,16 @@ class GhostOperator:
     """Matrix-free ghost penalty y = G(gamma) u on a Cartesian mesh cut by a level set.
 
     d, n, lo, h: mesh (cells per axis, lower corner, cell side); k: degree;
-    gamma: k coefficients; either (centre, radius) of a ball, or cell_class
-    (x-fastest array of 0 outside / 1 inside / 2 cut).  device=-1 builds a
+    gamma: k coefficients; either (centre, radius) of a ball, balls (a sequence of
+    (c0, c1, c2, r), their union), or cell_class (x-fastest array of 0 outside /
+    1 inside / 2 cut).  device=-1 builds a
     host-only plan (inspection without a GPU).
     """
 
     SCATTERS = ("box", "atomic", "coloured")
 
     def __init__(self, d, n, lo, h, k, gamma, centre=None, radius=None, cell_class=None,
-                 scatter="box", device=0):
+                 scatter="box", device=0, balls=None):
         lib = L.load()
         mesh = L.GhostMesh()
         mesh.dim = d
@@ -47,6 +48,12 @@ class GhostOperator:
             arr = np.ascontiguousarray(np.asarray(cell_class, dtype=np.int8).ravel())
             self._cls_keep = arr
             ls.cell_class = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_byte))
+        elif balls is not None:
+            ls.kind = L.GHOST_LS_BALLS
+            arr = np.ascontiguousarray(np.asarray(balls, dtype=np.float64).reshape(-1, 4))
+            self._cls_keep = arr
+            ls.n_balls = len(arr)
+            ls.balls = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         else:
             ls.kind = L.GHOST_LS_BALL
             for a in range(3):
@@ -73,7 +80,8 @@ class GhostOperator:
     @classmethod
     def from_workload(cls, w, scatter="box", device=0, gamma=None):
         return cls(w.d, w.n, w.lo, w.h, w.k, w.gamma() if gamma is None else gamma,
-                   centre=w.centre, radius=w.radius, scatter=scatter, device=device)
+                   centre=w.centre, radius=w.radius, scatter=scatter, device=device,
+                   balls=w.balls if w.balls else None)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

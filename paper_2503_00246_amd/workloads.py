@@ -26,6 +26,7 @@ class Workload:
     centre: tuple
     radius: float
     note: str = ""
+    balls: tuple = ()  # union of balls (c0, c1, c2, r) instead of the one ball (centre, radius)
 
     @property
     def h(self):
@@ -74,6 +75,22 @@ WORKLOADS = {
 def sweep_workload(k, n):
     """Same ball on an n^3 mesh of [-1,1]^3 with degree k (roofline sweeps)."""
     return Workload(f"ball3d_q{k}_{n}", 3, k, (n,) * 3, (-1.0,) * 3, BALL3, 0.73)
+
+
+SEED_BALLS = 6
+BALLS_R1 = 2.0
+
+
+def multiball_workload(k, n, n_balls, seed=SEED_BALLS):
+    """The multiple-ball problem (§3): the union of n_balls balls with centres drawn uniformly in
+    [-1,1]^3 (seeded; the centres of a smaller count are the first ones of a larger count) and the
+    common radius BALLS_R1 / n_balls, inversely proportional to the number of balls (one ball of
+    radius 2 covers most of the box), on an n^3 mesh of [-1,1]^3 with degree k."""
+    centres = np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n_balls, 3))
+    r = BALLS_R1 / n_balls
+    balls = tuple((float(c[0]), float(c[1]), float(c[2]), r) for c in centres)
+    return Workload(f"balls3d_q{k}_{n}_b{n_balls}", 3, k, (n,) * 3, (-1.0,) * 3, tuple(centres[0]), r,
+                    f"3D Q{k}, {n}^3 cells on [-1,1]^3, union of {n_balls} balls of radius {r:g}", balls)
 
 
 def submesh_q4_16():

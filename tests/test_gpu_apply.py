@@ -266,3 +266,55 @@ def test_apply_graph_replay():
         off[s] = False
         assert np.all(got[off] == 7.0)
         assert nerr(got32[s], r32[s]) <= TOL32
+
+
+def _multiball(name):
+    from paper_2503_00246_amd.workloads import multiball_workload
+    _, q, n, b = name.split("_")
+    return multiball_workload(int(q[1:]), int(n), int(b[1:]))
+
+
+@pytest.mark.parametrize("name", ["balls3d_q3_32_b8", "balls3d_q5_24_b4", "balls3d_q2_40_b32", "balls3d_q7_16_b2"])
+def test_multiball_parity(name):
+    """The multiple-ball problem (union of seeded balls, radius inversely proportional to their number):
+    FP64 and FP32 applies of every scatter against the oracle on the whole support, y untouched off it."""
+    w = _multiball(name)
+    o = GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), balls=w.balls)
+    u = uniform_vector(w.n_lattice, SEED_U)
+    ref, sup = o.apply(u), o.support()
+    ref32 = o.apply(u.astype(np.float32).astype(np.float64))
+    ut = torch.from_numpy(u).cuda()
+    off = np.ones(w.n_lattice, dtype=bool)
+    off[sup] = False
+    for scatter in SCATTERS:
+        op = gpu_op(w, scatter)
+        assert op.stats["n_faces_total"] == o.n_faces()
+        y = torch.full_like(ut, 3.0)
+        op.apply(ut, y, accumulate=False)
+        y = y.cpu().numpy()
+        assert nerr(y[sup], ref[sup]) <= TOL64, scatter
+        assert np.all(y[off] == 3.0), scatter
+        y32 = op.apply_f32(ut.float()).cpu().numpy().astype(np.float64)
+        assert nerr(y32[sup], ref32[sup]) <= TOL32, scatter
+
+
+def test_multiball_full_size_on_face_subset():
+    """128^3 Q3 with 8 balls, in the benchmark's launch configuration: y at every node of a seeded 1% face
+    sample's patches, the oracle summing all faces touching those nodes."""
+    w = _multiball("balls3d_q3_128_b8")
+    op = gpu_op(w)
+    o = GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), balls=w.balls)
+    faces_all = np.concatenate([np.c_[np.full(len(o.faces[a]), a), o.faces[a]] for a in range(3)])
+    pick = face_subset(len(faces_all))
+    from oracle import mesh
+    dofs = []
+    for a in range(3):
+        sel = pick[faces_all[pick, 0] == a]
+        offset = sum(len(o.faces[b]) for b in range(a))
+        if len(sel):
+            dofs.append(mesh.patch_dofs(o.faces[a][sel - offset], w.k, a, o.L).ravel())
+    dofs = np.unique(np.concatenate(dofs))
+    u = uniform_vector(w.n_lattice, SEED_U)
+    ref = o.apply_at(u, dofs)
+    y = op.apply(torch.from_numpy(u).cuda())[torch.from_numpy(dofs).cuda()].cpu().numpy()
+    assert nerr(y, ref) <= TOL64

@@ -35,6 +35,15 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, name)
 
 
+def _workload(name):
+    """A named workload, or a multiple-ball one named balls3d_q<k>_<n>_b<balls>."""
+    if name in WORKLOADS:
+        return WORKLOADS[name]
+    from paper_2503_00246_amd.workloads import multiball_workload
+    _, q, n, b = name.split("_")
+    return multiball_workload(int(q[1:]), int(n), int(b[1:]))
+
+
 def _host(w, scatter="box", **kw):
     return GhostOperator.from_workload(w, scatter=scatter, device=-1, **kw)
 
@@ -91,11 +100,12 @@ def test_generated_tables_match_runtime_tables():
         assert np.array_equal(Mv, np.asarray(t["mass"]).ravel())
 
 
-@pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64"])
+@pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64", "balls3d_q3_32_b8", "balls3d_q2_24_b16"])
 def test_plan_matches_oracle(name):
-    w = WORKLOADS[name]
+    w = _workload(name)
     op = _host(w)
-    cls = omesh.classify_ball(w.n, w.lo, w.h, w.centre, w.radius)
+    cls = (omesh.classify_balls(w.n, w.lo, w.h, w.balls) if w.balls
+           else omesh.classify_ball(w.n, w.lo, w.h, w.centre, w.radius))
     faces = omesh.ghost_faces(cls)
     st = op.stats
     assert st["n_active_cells"] == int(np.sum(cls != 0))
@@ -196,6 +206,17 @@ def _raw_setup(lib, dim=2, n=(8, 8, 8), h=0.25, k=2, gamma=(1.0, 1.0), kind=0, r
 def test_setup_rejects_bad_arguments(lib, kw, needle):
     rc, msg = _raw_setup(lib, **kw)
     assert rc == L.GHOST_EINVAL and needle in msg, msg
+
+
+@pytest.mark.parametrize("balls,needle", [
+    ([], "n_balls"), ([(0.0, 0.0, 0.0, -0.5)], "radius"), ([(0.0, 0.0, 0.0, 0.5), (float("nan"), 0.0, 0.0, 0.5)], "centre"),
+    ([(0.0, 0.0, 0.0, float("inf"))], "radius"),
+])
+def test_setup_rejects_bad_balls(balls, needle):
+    from paper_2503_00246_amd._lib import GhostError
+    with pytest.raises(GhostError, match=needle):
+        GhostOperator(3, (8, 8, 8), (-1, -1, -1), 0.25, 2, [1.0, 1.0], balls=np.array(balls, dtype=np.float64).reshape(-1, 4),
+                      device=-1)
 
 
 def test_bad_cell_class_value(lib):

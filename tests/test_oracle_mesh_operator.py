@@ -52,6 +52,47 @@ def test_classification_by_sampling(n, lo, h, centre, radius):
             assert np.all(r <= radius)
 
 
+UNIONS = [
+    ((16, 16, 16), (-1.0,) * 3, 2 / 16, [(0.31, -0.22, 0.05, 0.37), (-0.4, 0.3, -0.35, 0.52), (0.1, 0.12, 0.3, 0.29)]),
+    ((20, 18), (-1.0, -0.9), 2 / 20, [(0.213, 0.131, 0.0, 0.337), (-0.351, -0.207, 0.0, 0.419), (0.423, -0.509, 0.0, 0.271)]),
+]
+
+
+@pytest.mark.parametrize("n,lo,h,balls", UNIONS)
+def test_union_of_balls_classification(n, lo, h, balls):
+    """Union of balls: the same classes in any ball order; one ball alone reduces to classify_ball; by
+    sampling, a point strictly inside some ball makes a cell active, and an inside cell lies in one
+    ball as a whole (its corners, hence the cell, within that ball's radius)."""
+    d = len(n)
+    cls = mesh.classify_balls(n, lo, h, balls)
+    np.testing.assert_array_equal(cls, mesh.classify_balls(n, lo, h, balls[::-1]))
+    np.testing.assert_array_equal(mesh.classify_balls(n, lo, h, balls[:1]),
+                                  mesh.classify_ball(n, lo, h, balls[0][:d], balls[0][3]))
+    assert np.sum(cls == mesh.CUT) > 0 and np.sum(cls == mesh.INSIDE) > 0
+    s = (np.arange(7) + 0.5) / 7
+    grid = np.stack(np.meshgrid(*[s] * d, indexing="ij"), -1).reshape(-1, d)
+    corners = np.stack(np.meshgrid(*[[0.0, 1.0]] * d, indexing="ij"), -1).reshape(-1, d)
+    for c in np.ndindex(*n):
+        x = np.array(lo) + (np.array(c) + grid) * h
+        xc = np.array(lo) + (np.array(c) + corners) * h
+        r = np.stack([np.linalg.norm(x - np.array(b[:d]), axis=1) for b in balls])
+        rc = np.stack([np.linalg.norm(xc - np.array(b[:d]), axis=1) for b in balls])
+        radii = np.array([b[3] for b in balls])[:, None]
+        if np.any(r < radii):
+            assert cls[c] != mesh.OUTSIDE
+        if cls[c] == mesh.INSIDE:
+            assert np.any(np.all(rc <= radii, axis=1))
+        else:
+            assert not np.any(np.all(rc <= radii, axis=1))
+
+
+def test_union_cell_covered_only_jointly_is_cut():
+    """The reading for unions: the cell [0,1]^2 lies in the union of two balls (every point of it is
+    within 0.71 of one centre) but in neither ball alone, and is classified cut."""
+    cls = mesh.classify_balls((1, 1), (0.0, 0.0), 1.0, [(0.0, 0.5, 0.0, 0.8), (1.0, 0.5, 0.0, 0.8)])
+    assert cls[0, 0] == mesh.CUT
+
+
 def _gamma(k, h):
     return [0.5 * h ** (2 * j - 1) / math.factorial(j) ** 2 for j in range(1, k + 1)]
 
