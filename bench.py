@@ -52,9 +52,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="one JSON line per degree/mesh of the roofline sweep")
-    ap.add_argument("--mode", default="apply", choices=["apply", "vjp", "cg", "balls"],
+    ap.add_argument("--mode", default="apply", choices=["apply", "vjp", "cg", "balls", "micro"],
                     help="apply: the benchmark line; vjp: ghost_vjp on ball3d_q4_96; cg: FP64 vs mixed CG on "
-                         "ball3d_q7_96; balls: the multiple-ball problem, throughput against the cut fraction "
+                         "ball3d_q7_96; balls: the multiple-ball problem, throughput against the cut fraction; "
+                         "micro: the single-face compute-bound microbenchmark, d = 2, 3 and k = 1..7 "
                          "(extra lines, not the benchmark metric)")
     ap.add_argument("--balls-k", type=int, default=3, help="degree of the multiple-ball problem")
     ap.add_argument("--balls-n", type=int, default=128, help="cells per axis of the multiple-ball problem")
@@ -257,6 +258,48 @@ def run_cg(w, args):
         print(json.dumps(out), flush=True)
 
 
+def run_micro(args, blocks=2048, reps=100):
+    """Single-face microbenchmark: `blocks` workgroups of faces, each face's operator applied `reps`
+    times to resident values (no gather, no scatter); time per face application, flop rate against the
+    vector peak of the precision, and the time relative to k = 1 (the paper's presentation)."""
+    import torch
+    from paper_2503_00246_amd.operator import GhostOperator
+    from paper_2503_00246_amd.workloads import gamma_paper
+    peak = {torch.float64: 78.6e12, torch.float32: 157.3e12}
+    for d in (2, 3):
+        base = {}
+        for k in range(1, 8):
+            h = 0.25
+            op = GhostOperator(d, (8,) * d, (-1.0,) * d, h, k, gamma_paper(k, h),
+                               centre=(0.011, 0.017, 0.023)[:d], radius=0.73)
+            nn, tl = 2 * k + 1, (k + 1) ** (d - 1)
+            nf = blocks * 8 * (64 // tl)
+            flops = op.stats["flops_per_face"]
+            line = {"metric": "single-face ghost-penalty application (compute-bound microbenchmark)",
+                    "d": d, "k": k, "faces": nf, "reps": reps, "flops_per_face": flops}
+            for dt in (torch.float64, torch.float32):
+                x = torch.rand((nf, nn, tl), dtype=dt, device="cuda") * 2 - 1
+                y = torch.empty_like(x)
+                op.face_bench(x, y, reps=reps)
+                torch.cuda.synchronize()
+                start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                start.record()
+                op.face_bench(x, y, reps=reps)
+                end.record()
+                torch.cuda.synchronize()
+                t = start.elapsed_time(end) / 1e3
+                per = t / (nf * reps)
+                key = "fp64" if dt == torch.float64 else "fp32"
+                base.setdefault(key, per)
+                line[key] = {"ns_per_face": round(per * 1e9, 5), "tflops": round(flops / per / 1e12, 3),
+                             "frac_of_vector_peak": round(flops / per / peak[dt], 4),
+                             "relative_to_k1": round(per / base[key], 3)}
+                del x, y
+            print(json.dumps(line), flush=True)
+            del op
+            torch.cuda.empty_cache()
+
+
 def run_balls(args):
     """The multiple-ball problem: one line per ball count, with the cut fraction of the active cells."""
     from paper_2503_00246_amd.workloads import multiball_workload
@@ -299,6 +342,9 @@ def main():
         return
     if args.mode == "balls":
         run_balls(args)
+        return
+    if args.mode == "micro":
+        run_micro(args)
         return
     if args.sweep:
         for k, n in [(3, 128), (3, 96), (4, 96), (5, 96), (5, 128), (6, 96), (7, 96)]:

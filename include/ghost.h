@@ -182,6 +182,19 @@ int ghost_mass_diag(ghost_ctx *ctx, double *diag, void *stream);
  */
 int ghost_diag(ghost_ctx *ctx, double *diag, int accumulate, void *stream);
 
+/*
+ * Single-face microbenchmark (the computational-efficiency experiment of §3, ghost-penalty column):
+ * for n_faces independent faces, out = reps * G_F in, each face's operator applied `reps` times to the
+ * same values by the apply's per-face pipeline (normal contraction, tangential masses, expansion),
+ * without the gather from the lattice and the scatter, so the run is compute-bound.  G_F is the face
+ * operator of the context's d, k, h and gamma in the face's local coordinates (the same for every
+ * normal axis).  in, out: DEVICE arrays of n_faces * (2k+1) * (k+1)^(d-1) values in the layout
+ * [face][normal node i = 0..2k][tangential line t], t = t1 + (k+1) t2 with t1, t2 along the tangential
+ * axes in increasing order; out is overwritten.  n_faces >= 0, reps >= 1.  Stream-ordered.
+ */
+int ghost_face_bench(ghost_ctx *ctx, const double *in, double *out, int64_t n_faces, int reps, void *stream);
+int ghost_face_bench_f32(ghost_ctx *ctx, const float *in, float *out, int64_t n_faces, int reps, void *stream);
+
 /* Conjugate gradients on (M + G) x = b over the active nodes (M as in ghost_mass_diag). */
 #define GHOST_CG_FP64 0  /* plain FP64 CG */
 #define GHOST_CG_MIXED 1 /* FP64 outer refinement of the true residual, FP32 inner CG */

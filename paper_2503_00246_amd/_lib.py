@@ -18,7 +18,8 @@ GHOST_CG_NONE, GHOST_CG_JACOBI = 0, 1
 
 EXPORTS = ["ghost_setup", "ghost_set_gamma", "ghost_apply", "ghost_apply_f32", "ghost_vjp",
            "ghost_mass_diag", "ghost_cg", "ghost_info", "ghost_faces", "ghost_tables", "ghost_box_layout",
-           "ghost_destroy", "ghost_last_error", "ghost_set_timing", "ghost_kernel_times", "ghost_diag"]
+           "ghost_destroy", "ghost_last_error", "ghost_set_timing", "ghost_kernel_times", "ghost_diag",
+           "ghost_face_bench", "ghost_face_bench_f32"]
 
 
 class GhostMesh(ctypes.Structure):
@@ -89,6 +90,8 @@ def load(path=LIB_PATH):
     lib.ghost_vjp.argtypes = [P, P, P, P, P, c_int, P]
     lib.ghost_mass_diag.argtypes = [P, P, P]
     lib.ghost_diag.argtypes = [P, P, c_int, P]
+    lib.ghost_face_bench.argtypes = [P, P, P, c_i64, c_int, P]
+    lib.ghost_face_bench_f32.argtypes = [P, P, P, c_i64, c_int, P]
     lib.ghost_cg.argtypes = [P, P, P, ctypes.POINTER(GhostCgOpts), ctypes.POINTER(GhostCgResult), P]
     lib.ghost_info.argtypes = [P, ctypes.POINTER(GhostStats)]
     lib.ghost_faces.argtypes = [P, c_int, ctypes.POINTER(ctypes.c_int32), c_i64]

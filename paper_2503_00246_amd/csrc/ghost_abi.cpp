@@ -424,6 +424,35 @@ int ghost_diag(ghost_ctx *ctx, double *diag, int accumulate, void *stream) {
   return e == hipSuccess ? GHOST_OK : fail_hip(e, "diag launch");
 }
 
+extern "C++" {
+template <typename T>
+int face_bench(ghost_ctx *ctx, const T *in, T *out, int64_t n_faces, int reps, void *stream) {
+  if (!ctx || (n_faces > 0 && (!in || !out))) return fail(GHOST_EINVAL, "null context, in or out");
+  if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");
+  if (n_faces < 0 || reps < 1) return fail(GHOST_EINVAL, "need n_faces >= 0 and reps >= 1");
+  int64_t n_p = 2 * ctx->plan.k + 1;
+  for (int a = 1; a < ctx->plan.dim; ++a) n_p *= ctx->plan.k + 1;
+  if (n_faces > ((int64_t)1 << 40) / n_p) return fail(GHOST_EINVAL, "n_faces too large");
+  if (n_faces > 0 && (const void *)in == (const void *)out) return fail(GHOST_EINVAL, "in and out must differ");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  hipError_t e;
+  if constexpr (sizeof(T) == 8)
+    e = ghost::launch_face_micro(ctx->dev, in, out, n_faces, reps, static_cast<hipStream_t>(stream));
+  else
+    e = ghost::launch_face_micro_f32(ctx->dev, in, out, n_faces, reps, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GHOST_OK : fail_hip(e, "face_bench launch");
+}
+}  // extern "C++"
+
+int ghost_face_bench(ghost_ctx *ctx, const double *in, double *out, int64_t n_faces, int reps, void *stream) {
+  return face_bench<double>(ctx, in, out, n_faces, reps, stream);
+}
+
+int ghost_face_bench_f32(ghost_ctx *ctx, const float *in, float *out, int64_t n_faces, int reps, void *stream) {
+  return face_bench<float>(ctx, in, out, n_faces, reps, stream);
+}
+
 int ghost_mass_diag(ghost_ctx *ctx, double *diag, void *stream) {
   if (!ctx || !diag) return fail(GHOST_EINVAL, "null context or diag");
   if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");

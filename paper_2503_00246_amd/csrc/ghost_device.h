@@ -87,5 +87,10 @@ hipError_t launch_set_gamma_host(const DevPlan &p, GammaArg g, hipStream_t s);
 hipError_t launch_mass_diag(const DevPlan &p, double *diag, hipStream_t s);
 hipError_t launch_ghost_diag(const DevPlan &p, double *diag, hipStream_t s);  // diag += diag(G)
 hipError_t launch_zero_support(const DevPlan &p, double *y, hipStream_t s);
+// single-face microbenchmark: out = reps * G_F in per face, local layout [normal node][tangential line]
+hipError_t launch_face_micro(const DevPlan &p, const double *in, double *out, int64_t n_faces, int reps,
+                             hipStream_t s);
+hipError_t launch_face_micro_f32(const DevPlan &p, const float *in, float *out, int64_t n_faces, int reps,
+                                 hipStream_t s);
 
 }  // namespace ghost

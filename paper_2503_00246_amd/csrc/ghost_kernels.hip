@@ -391,6 +391,129 @@ __device__ __forceinline__ void copy_box_records(const Visit *__restrict__ visit
                                      lds_ptr(reinterpret_cast<char *>(slines_dst) + 16 * wbase), 16, 0, 0);
 }
 
+// The per-face rank-k pipeline, one wave slot (a face's tangential lines) at a time; the box kernel and
+// the single-face microbenchmark share it.  Tab1d<K> holds the reference jump vectors g and mass M.
+template <typename T, int K, bool VJP>
+__device__ __forceinline__ void face_contract(const T (&line)[2 * K - 1], const T (&uline)[2 * K - 1], T (&a)[K - 1],
+                                              T (&au)[K - 1]) {
+  constexpr int k = K - 1, NN = 2 * k + 1;
+  using Tab = gen::Tab1d<K>;
+  // normal contraction a_j = g_j . line, folded with the reflection symmetry g_j[2k-i] = (-1)^(j+1)
+  // g_j[i] (derivative order j+1 odd for even j here: those rows use the sums, the others the
+  // differences); rows of dead faces are computed on node-0 data and never expanded
+  {
+    T ev[k], od[k], eu[k], ou[k];
+#pragma unroll
+    for (int i = 0; i < k; ++i) {
+      ev[i] = line[i] + line[2 * k - i];
+      od[i] = line[i] - line[2 * k - i];
+      if (VJP) {
+        eu[i] = uline[i] + uline[2 * k - i];
+        ou[i] = uline[i] - uline[2 * k - i];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < k; ++j) {
+      T s, su = T(0);
+      if (j % 2 == 0) {
+        s = T(Tab::g[j * NN + k]) * line[k];
+        if (VJP) su = T(Tab::g[j * NN + k]) * uline[k];
+#pragma unroll
+        for (int i = 0; i < k; ++i) {
+          s = fma(T(Tab::g[j * NN + i]), ev[i], s);
+          if (VJP) su = fma(T(Tab::g[j * NN + i]), eu[i], su);
+        }
+      } else {
+        s = T(0);
+#pragma unroll
+        for (int i = 0; i < k; ++i) {
+          s = fma(T(Tab::g[j * NN + i]), od[i], s);
+          if (VJP) su = fma(T(Tab::g[j * NN + i]), ou[i], su);
+        }
+      }
+      a[j] = s;
+      au[j] = su;
+    }
+  }
+}
+
+template <typename T, int D, int K>
+__device__ __forceinline__ void face_masses(T *sa, int f, int t, int t1, int t2, bool in_block) {
+  constexpr int k = K - 1, TL = lines_per_face(D, k);
+  using Tab = gen::Tab1d<K>;
+  // tangential masses in place: each row (column) is read and rewritten by the one thread that owns
+  // it, and the wavefront fence between the passes orders the row writes before the column reads
+  if (D == 3) {
+    if (in_block && t1 < k) {
+      T *row = &sa[(f * k + t1) * TL + t2 * K];
+      T r[K];
+#pragma unroll
+      for (int m = 0; m < K; ++m) r[m] = row[m];
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        T s = T(0);
+#pragma unroll
+        for (int m = 0; m < K; ++m) s = fma(T(Tab::M[q * K + m]), r[m], s);
+        row[q] = s;
+      }
+    }
+    wave_sync();
+    if (in_block && t2 < k) {
+      T *col = &sa[(f * k + t2) * TL + t1];
+      T r[K];
+#pragma unroll
+      for (int m = 0; m < K; ++m) r[m] = col[m * K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        T s = T(0);
+#pragma unroll
+        for (int m = 0; m < K; ++m) s = fma(T(Tab::M[q * K + m]), r[m], s);
+        col[q * K] = s;
+      }
+    }
+    wave_sync();
+  } else {
+    if (in_block && t < k) {
+      T *row = &sa[(f * k + t) * TL];
+      T r[K];
+#pragma unroll
+      for (int m = 0; m < K; ++m) r[m] = row[m];
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        T s = T(0);
+#pragma unroll
+        for (int m = 0; m < K; ++m) s = fma(T(Tab::M[q * K + m]), r[m], s);
+        row[q] = s;
+      }
+    }
+    wave_sync();
+  }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void face_expand(const T (&cj)[K - 1], const T (&coef)[K - 1], T (&yv2)[2 * K - 1]) {
+  constexpr int k = K - 1, NN = 2 * k + 1;
+  using Tab = gen::Tab1d<K>;
+  // expansion y_i = sum_j coef_j g_j[i] c_j (coef_j = gamma_j h^{d-1-2j}), folded: E_i from the
+  // symmetric orders, O_i from the others, y_i = E_i + O_i and y_{2k-i} = E_i - O_i
+  T cs[k];
+#pragma unroll
+  for (int j = 0; j < k; ++j) cs[j] = coef[j] * cj[j];
+#pragma unroll
+  for (int i = 0; i <= k; ++i) {
+    T e = T(0), o = T(0);
+#pragma unroll
+    for (int j = 0; j < k; ++j) {
+      if (j % 2 == 0)
+        e = fma(T(Tab::g[j * NN + i]), cs[j], e);
+      else if (i < k)
+        o = fma(T(Tab::g[j * NN + i]), cs[j], o);
+    }
+    yv2[i] = e + o;
+    if (i < k) yv2[2 * k - i] = e - o;
+  }
+}
+
 // Flush plan of a box, one packed word per flush line of the lane: -1 when the lane's node is not
 // touched, else the box line index (bits 0-7), a shared flag (bit 8) and, for a shared node, its halo
 // slot relative to the box's first (bits 9-21).  All records are read before any is decoded, and the
@@ -553,44 +676,8 @@ __device__ __forceinline__ void box_body(
         uline[i] = VJP ? unext[i] : T(0);
       }
 
-      // normal contraction a_j = g_j . line, folded with the reflection symmetry g_j[2k-i] = (-1)^(j+1)
-      // g_j[i] (derivative order j+1 odd for even j here: those rows use the sums, the others the
-      // differences); rows of dead faces are computed on node-0 data and never expanded
       T a[k], au[k];
-      {
-        T ev[k], od[k], eu[k], ou[k];
-#pragma unroll
-        for (int i = 0; i < k; ++i) {
-          ev[i] = line[i] + line[2 * k - i];
-          od[i] = line[i] - line[2 * k - i];
-          if (VJP) {
-            eu[i] = uline[i] + uline[2 * k - i];
-            ou[i] = uline[i] - uline[2 * k - i];
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < k; ++j) {
-          T s, su = T(0);
-          if (j % 2 == 0) {
-            s = T(Tab::g[j * NN + k]) * line[k];
-            if (VJP) su = T(Tab::g[j * NN + k]) * uline[k];
-#pragma unroll
-            for (int i = 0; i < k; ++i) {
-              s = fma(T(Tab::g[j * NN + i]), ev[i], s);
-              if (VJP) su = fma(T(Tab::g[j * NN + i]), eu[i], su);
-            }
-          } else {
-            s = T(0);
-#pragma unroll
-            for (int i = 0; i < k; ++i) {
-              s = fma(T(Tab::g[j * NN + i]), od[i], s);
-              if (VJP) su = fma(T(Tab::g[j * NN + i]), ou[i], su);
-            }
-          }
-          a[j] = s;
-          au[j] = su;
-        }
-      }
+      face_contract<T, K, VJP>(line, uline, a, au);
       if (in_block) {
 #pragma unroll
         for (int j = 0; j < k; ++j) sa[(f * k + j) * TL + t] = a[j];
@@ -612,76 +699,13 @@ __device__ __forceinline__ void box_body(
         if (VJP) gather_line<T, NN>(u2 + (box_base + glo), nxp.gofs, nxp.sn, unext);
         if (b == 0 && nxt >= 0) copy_box_records<kLinesMax>(visits, lines, bn, &svis[buf ^ 1][0], slines, tid);
       }
-      // tangential masses in place: each row (column) is read and rewritten by the one thread that owns
-      // it, and the barrier between the passes orders the row writes before the column reads
-      if (D == 3) {
-        if (in_block && t1 < k) {
-          T *row = &sa[(f * k + t1) * TL + t2 * K];
-          T r[K];
-#pragma unroll
-          for (int m = 0; m < K; ++m) r[m] = row[m];
-#pragma unroll
-          for (int q = 0; q < K; ++q) {
-            T s = T(0);
-#pragma unroll
-            for (int m = 0; m < K; ++m) s = fma(T(Tab::M[q * K + m]), r[m], s);
-            row[q] = s;
-          }
-        }
-        wave_sync();
-        if (in_block && t2 < k) {
-          T *col = &sa[(f * k + t2) * TL + t1];
-          T r[K];
-#pragma unroll
-          for (int m = 0; m < K; ++m) r[m] = col[m * K];
-#pragma unroll
-          for (int q = 0; q < K; ++q) {
-            T s = T(0);
-#pragma unroll
-            for (int m = 0; m < K; ++m) s = fma(T(Tab::M[q * K + m]), r[m], s);
-            col[q * K] = s;
-          }
-        }
-        wave_sync();
-      } else {
-        if (in_block && t < k) {
-          T *row = &sa[(f * k + t) * TL];
-          T r[K];
-#pragma unroll
-          for (int m = 0; m < K; ++m) r[m] = row[m];
-#pragma unroll
-          for (int q = 0; q < K; ++q) {
-            T s = T(0);
-#pragma unroll
-            for (int m = 0; m < K; ++m) s = fma(T(Tab::M[q * K + m]), r[m], s);
-            row[q] = s;
-          }
-        }
-        wave_sync();
-      }
+      face_masses<T, D, K>(sa, f, t, t1, t2, in_block);
       T cj[k];
 #pragma unroll
       for (int j = 0; j < k; ++j) cj[j] = in_block ? sa[(f * k + j) * TL + t] : T(0);
       if (cur_p.live) {
-        // expansion y_i = sum_j coef_j g_j[i] c_j (coef_j = gamma_j h^{d-1-2j}), folded: E_i from the
-        // symmetric orders, O_i from the others, y_i = E_i + O_i and y_{2k-i} = E_i - O_i
-        T cs[k];
-#pragma unroll
-        for (int j = 0; j < k; ++j) cs[j] = coef[j] * cj[j];
         T yv2[NN];
-#pragma unroll
-        for (int i = 0; i <= k; ++i) {
-          T e = T(0), o = T(0);
-#pragma unroll
-          for (int j = 0; j < k; ++j) {
-            if (j % 2 == 0)
-              e = fma(T(Tab::g[j * NN + i]), cs[j], e);
-            else if (i < k)
-              o = fma(T(Tab::g[j * NN + i]), cs[j], o);
-          }
-          yv2[i] = e + o;
-          if (i < k) yv2[2 * k - i] = e - o;
-        }
+        face_expand<T, K>(cj, coef, yv2);
         if (cur_p.lo) {
           int off = cur_p.acc0;
 #pragma unroll
@@ -1041,6 +1065,88 @@ hipError_t run_faces_marked(const DevPlan &p, const T *x, const T *u2, T *y, con
 }
 
 }  // namespace
+
+// Single-face microbenchmark, compute-bound (the computational-efficiency experiment of §3, ghost
+// penalty only): every wave slot applies its face's operator to the same patch values `reps` times with
+// the box kernel's per-face pipeline (the values are made opaque to the compiler before each repetition,
+// so that none is folded away) and writes the sum, out = reps * G_F in.  Layout per face: [normal node
+// i][tangential line t], t = t1 + (k+1) t2.  No gather from the lattice and no scatter.
+template <typename T, int D, int K>
+__global__ __launch_bounds__(kBoxThreads) void face_micro_kernel(const T *__restrict__ in, T *__restrict__ out,
+                                                                 const T *__restrict__ tab, int64_t n_faces,
+                                                                 int reps) {
+  constexpr int k = K - 1, NN = 2 * k + 1;
+  constexpr int TL = lines_per_face(D, k), FW = 64 / TL, FPB = box_faces_per_batch(D, k);
+  __shared__ T sa[FPB * k * TL];
+  const int tid = threadIdx.x, lane_w = tid & 63, fw = lane_w / TL;
+  const int f = (tid >> 6) * FW + fw, t = lane_w - fw * TL;
+  const bool in_block = fw < FW;
+  const int t1 = (D == 3) ? t % K : t;
+  const int t2 = (D == 3) ? t / K : 0;
+  const int64_t face = (int64_t)blockIdx.x * FPB + f;
+  const bool live = in_block && face < n_faces;
+  T coef[k];
+#pragma unroll
+  for (int j = 0; j < k; ++j) coef[j] = tab[tab_coef(k) + j];
+  T line[NN], acc[NN];
+#pragma unroll
+  for (int i = 0; i < NN; ++i) {
+    line[i] = live ? in[(face * NN + i) * TL + t] : T(0);
+    acc[i] = T(0);
+  }
+  for (int r = 0; r < reps; ++r) {
+#pragma unroll
+    for (int i = 0; i < NN; ++i) asm volatile("" : "+v"(line[i]));
+    T a[k], au[k];
+    face_contract<T, K, false>(line, line, a, au);
+    if (in_block) {
+#pragma unroll
+      for (int j = 0; j < k; ++j) sa[(f * k + j) * TL + t] = a[j];
+    }
+    wave_sync();
+    face_masses<T, D, K>(sa, f, t, t1, t2, in_block);
+    T cj[k];
+#pragma unroll
+    for (int j = 0; j < k; ++j) cj[j] = in_block ? sa[(f * k + j) * TL + t] : T(0);
+    T yv2[NN];
+    face_expand<T, K>(cj, coef, yv2);
+#pragma unroll
+    for (int i = 0; i < NN; ++i) acc[i] += yv2[i];
+    wave_sync();  // sa is rewritten by the next repetition
+  }
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < NN; ++i) out[(face * NN + i) * TL + t] = acc[i];
+  }
+}
+
+template <typename T>
+hipError_t launch_face_micro_t(const DevPlan &p, const T *in, T *out, const T *tab, int64_t n_faces, int reps,
+                               hipStream_t s) {
+  if (n_faces == 0) return hipSuccess;
+  hipError_t e = hipErrorInvalidValue;
+#define GHOST_MCASE(D_, K_)                                                                               \
+  if (p.dim == D_ && p.k + 1 == K_) {                                                                      \
+    const int64_t fpb = box_faces_per_batch(D_, K_ - 1);                                                   \
+    hipLaunchKernelGGL((face_micro_kernel<T, D_, K_>), dim3((unsigned)((n_faces + fpb - 1) / fpb)),       \
+                       dim3(kBoxThreads), 0, s, in, out, tab, n_faces, reps);                              \
+    e = hipGetLastError();                                                                                 \
+  }
+  GHOST_MCASE(2, 2) GHOST_MCASE(2, 3) GHOST_MCASE(2, 4) GHOST_MCASE(2, 5) GHOST_MCASE(2, 6) GHOST_MCASE(2, 7)
+  GHOST_MCASE(2, 8) GHOST_MCASE(3, 2) GHOST_MCASE(3, 3) GHOST_MCASE(3, 4) GHOST_MCASE(3, 5) GHOST_MCASE(3, 6)
+  GHOST_MCASE(3, 7) GHOST_MCASE(3, 8)
+#undef GHOST_MCASE
+  return e;
+}
+
+hipError_t launch_face_micro(const DevPlan &p, const double *in, double *out, int64_t n_faces, int reps,
+                             hipStream_t s) {
+  return launch_face_micro_t<double>(p, in, out, p.tab64, n_faces, reps, s);
+}
+hipError_t launch_face_micro_f32(const DevPlan &p, const float *in, float *out, int64_t n_faces, int reps,
+                                 hipStream_t s) {
+  return launch_face_micro_t<float>(p, in, out, p.tab32, n_faces, reps, s);
+}
 
 hipError_t launch_apply_f64(const DevPlan &p, const double *u, double *y, bool accumulate, hipStream_t s) {
   if (p.scatter == Scatter::Box) return dispatch_box<double, false>(p, u, nullptr, y, p.tab64, accumulate, s);

@@ -122,6 +122,25 @@ class GhostOperator:
         L.check(self._lib.ghost_apply(self._h, _ptr(u), _ptr(y), int(accumulate), _stream(self._dev())))
         return y
 
+    def face_bench(self, inp, out=None, reps=1):
+        """Single-face microbenchmark: out = reps * G_F inp for every face of inp, a float64 or float32
+        CUDA tensor of shape (n_faces, 2k+1, (k+1)^(d-1)) in the face's local layout [normal node][line]."""
+        import torch
+        n_p = (2 * self.k + 1) * (self.k + 1) ** (self.d - 1)
+        if not isinstance(inp, torch.Tensor) or inp.dtype not in (torch.float64, torch.float32):
+            raise TypeError("inp must be a float64 or float32 torch tensor")
+        if inp.device.type != "cuda" or inp.device.index != self.device or not inp.is_contiguous():
+            raise ValueError(f"inp must be contiguous on cuda:{self.device}")
+        if inp.numel() % n_p:
+            raise ValueError(f"inp must hold whole faces of {n_p} values")
+        if out is None:
+            out = torch.empty_like(inp)
+        if out.dtype != inp.dtype or out.shape != inp.shape or not out.is_contiguous():
+            raise ValueError("out must match inp")
+        fn = self._lib.ghost_face_bench if inp.dtype == torch.float64 else self._lib.ghost_face_bench_f32
+        L.check(fn(self._h, _ptr(inp), _ptr(out), inp.numel() // n_p, int(reps), _stream(self._dev())))
+        return out
+
     def apply_f32(self, u, y=None, accumulate=False):
         import torch
         self._vec(u, torch.float32, "u")
