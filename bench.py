@@ -52,10 +52,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="one JSON line per degree/mesh of the roofline sweep")
-    ap.add_argument("--mode", default="apply", choices=["apply", "vjp", "cg", "balls", "micro"],
+    ap.add_argument("--mode", default="apply", choices=["apply", "vjp", "cg", "balls", "micro", "cell"],
                     help="apply: the benchmark line; vjp: ghost_vjp on ball3d_q4_96; cg: FP64 vs mixed CG on "
                          "ball3d_q7_96; balls: the multiple-ball problem, throughput against the cut fraction; "
-                         "micro: the single-face compute-bound microbenchmark, d = 2, 3 and k = 1..7 "
+                         "micro: the single-face compute-bound microbenchmark, d = 2, 3 and k = 1..7; "
+                         "cell: the interior-cell Laplacian and (K_inside + G) u on the workload "
                          "(extra lines, not the benchmark metric)")
     ap.add_argument("--balls-k", type=int, default=3, help="degree of the multiple-ball problem")
     ap.add_argument("--balls-n", type=int, default=128, help="cells per axis of the multiple-ball problem")
@@ -258,6 +259,40 @@ def run_cg(w, args):
         print(json.dumps(out), flush=True)
 
 
+def run_cell(w, args):
+    """The interior-cell Laplacian (y += K_inside u) and the operator without its cut-cell part,
+    (K_inside + G) u, timed like the apply.  Metrics: cell DoFs per second (inside cells x (k+1)^d / t)
+    and, for the whole operator, active DoFs per second; bytes: 24 per inside node (u read, y read and
+    written) for the cell operator."""
+    import torch
+    from paper_2503_00246_amd.operator import GhostOperator
+    from paper_2503_00246_amd.workloads import SEED_U, uniform_vector
+    op = GhostOperator.from_workload(w, scatter=args.scatter)
+    st = op.stats
+    n_inside = st["n_active_cells"] - st["n_cut_cells"]
+    cell_dofs = n_inside * (w.k + 1) ** w.d
+    u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda()
+    out = {"metric": "interior-cell Laplacian and (K_inside + G) u", "workload": w.name, "inside_cells": n_inside,
+           "inside_dofs": st["n_inside_dofs"], "active_dofs": st["n_active_dofs"], "steps": args.steps}
+    for dt, key, elem in ((torch.float64, "fp64", 8), (torch.float32, "fp32", 4)):
+        uu = u.to(dt)
+        y = torch.zeros_like(uu)
+        t_cell = timed_applies(lambda: op.cell_apply(uu, y), args.steps, args.warmup)
+        if dt == torch.float64:
+            t_sys = timed_applies(lambda: (op.cell_apply(uu, y), op.apply(uu, y, accumulate=True)), args.steps,
+                                  args.warmup)
+        else:
+            t_sys = timed_applies(lambda: (op.cell_apply(uu, y), op.apply_f32(uu, y, accumulate=True)), args.steps,
+                                  args.warmup)
+        alg = 3 * elem * st["n_inside_dofs"]
+        out[key] = {"cell_ms": round(t_cell * 1e3, 5), "cell_gdofs": round(cell_dofs / t_cell / 1e9, 3),
+                    "cell_GBps": round(alg / t_cell / 1e9, 1), "cell_frac": round(alg / t_cell / 1e9 / HBM_PEAK_GBS, 4),
+                    "system_ms": round(t_sys * 1e3, 5),
+                    "system_active_gdofs": round(st["n_active_dofs"] / t_sys / 1e9, 3)}
+        del uu, y
+    print(json.dumps(out), flush=True)
+
+
 def run_micro(args, blocks=2048, reps=100):
     """Single-face microbenchmark: `blocks` workgroups of faces, each face's operator applied `reps`
     times to resident values (no gather, no scatter); time per face application, flop rate against the
@@ -345,6 +380,9 @@ def main():
         return
     if args.mode == "micro":
         run_micro(args)
+        return
+    if args.mode == "cell":
+        run_cell(WORKLOADS[args.workload], args)
         return
     if args.sweep:
         for k, n in [(3, 128), (3, 96), (4, 96), (5, 96), (5, 128), (6, 96), (7, 96)]:

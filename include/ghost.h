@@ -115,6 +115,7 @@ typedef struct {
   double flops_per_face;      /* arithmetic of one face in the kernel, 2 per FMA */
   double bytes_fp64;          /* compulsory bytes of an accumulating FP64 apply: 24 per support DoF */
   double bytes_fp32;          /* same for FP32: 12 per support DoF */
+  int64_t n_inside_dofs;      /* nodes of inside cells (the interior Laplacian's nodes) */
 } ghost_stats;
 
 /*
@@ -181,6 +182,18 @@ int ghost_mass_diag(ghost_ctx *ctx, double *diag, void *stream);
  * preconditioner set-up, not for the hot loop).
  */
 int ghost_diag(ghost_ctx *ctx, double *diag, int accumulate, void *stream);
+
+/*
+ * Interior-cell Laplacian (the cell term of the weak form, §2.1, on the cells the boundary does not cut,
+ * evaluated by sum factorisation as in §2.5 and Algorithm 1):
+ *   y += sum over INSIDE cells K of K_K u_K,  [K_K]_ab = integral_K grad phi_a . grad phi_b,
+ * so that ghost_cell_apply followed by ghost_apply (accumulate = 1) gives (K_inside + G) u, the
+ * operator of the paper's vmult without its cut-cell part.  u, y: DEVICE arrays of n_lattice values
+ * (u != y); y is only added to (pass a zeroed y for K_inside u).  Stream-ordered; one launch per parity
+ * colour of the cells (cells of a colour share no node), no atomics.
+ */
+int ghost_cell_apply(ghost_ctx *ctx, const double *u, double *y, void *stream);
+int ghost_cell_apply_f32(ghost_ctx *ctx, const float *u, float *y, void *stream);
 
 /*
  * Single-face microbenchmark (the computational-efficiency experiment of §3, ghost-penalty column):

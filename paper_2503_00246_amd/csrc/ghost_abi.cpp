@@ -257,6 +257,10 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
     if (rc == GHOST_OK) rc = upload(c, p.support_runs.data(), p.support_runs.size(), const_cast<ghost::Run **>(&sr));
     if (rc == GHOST_OK) rc = upload(c, p.active_runs.data(), p.active_runs.size(), const_cast<ghost::Run **>(&ar));
     if (rc == GHOST_OK) rc = upload(c, p.cls.data(), p.cls.size(), const_cast<int8_t **>(&cl));
+    const int64_t *ib = nullptr;
+    if (rc == GHOST_OK) rc = upload(c, p.inside_base.data(), p.inside_base.size(), const_cast<int64_t **>(&ib));
+    d.inside_base = ib;
+    for (int q = 0; q <= 8; ++q) d.inside_colour_begin[q] = p.inside_colour_begin[q];
     if (rc == GHOST_OK) rc = upload(c, t64.data(), t64.size(), &d.tab64);
     if (rc == GHOST_OK) rc = upload(c, t32.data(), t32.size(), &d.tab32);
     const ghost::Box *bxv = nullptr;
@@ -445,6 +449,24 @@ int face_bench(ghost_ctx *ctx, const T *in, T *out, int64_t n_faces, int reps, v
 }
 }  // extern "C++"
 
+int ghost_cell_apply(ghost_ctx *ctx, const double *u, double *y, void *stream) {
+  int rc = check_apply(ctx, u, y, sizeof(double));
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  hipError_t e = ghost::launch_cell_apply(ctx->dev, u, y, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GHOST_OK : fail_hip(e, "cell_apply launch");
+}
+
+int ghost_cell_apply_f32(ghost_ctx *ctx, const float *u, float *y, void *stream) {
+  int rc = check_apply(ctx, u, y, sizeof(float));
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(g.err, "hipSetDevice");
+  hipError_t e = ghost::launch_cell_apply_f32(ctx->dev, u, y, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GHOST_OK : fail_hip(e, "cell_apply_f32 launch");
+}
+
 int ghost_face_bench(ghost_ctx *ctx, const double *in, double *out, int64_t n_faces, int reps, void *stream) {
   return face_bench<double>(ctx, in, out, n_faces, reps, stream);
 }
@@ -481,6 +503,7 @@ int ghost_info(const ghost_ctx *ctx, ghost_stats *out) {
   out->n_cut_cells = p.n_cut_cells;
   out->n_active_dofs = p.n_active;
   out->n_support_dofs = p.n_support;
+  out->n_inside_dofs = p.n_inside;
   const int K = p.k + 1;
   int64_t tang = 1;
   for (int a = 1; a < p.dim; ++a) tang *= K;

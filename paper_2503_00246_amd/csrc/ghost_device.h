@@ -70,6 +70,10 @@ struct DevPlan {
   // and after it (all null: no records)
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 
+  // inside cells of the interior Laplacian (first-node lattice index), by parity colour
+  const int64_t *inside_base = nullptr;
+  int64_t inside_colour_begin[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+
   double *tab64 = nullptr;
   float *tab32 = nullptr;
   double *vjp_partial = nullptr;      // max(n_batches, n_boxes) * k doubles
@@ -87,6 +91,9 @@ hipError_t launch_set_gamma_host(const DevPlan &p, GammaArg g, hipStream_t s);
 hipError_t launch_mass_diag(const DevPlan &p, double *diag, hipStream_t s);
 hipError_t launch_ghost_diag(const DevPlan &p, double *diag, hipStream_t s);  // diag += diag(G)
 hipError_t launch_zero_support(const DevPlan &p, double *y, hipStream_t s);
+// interior-cell Laplacian: y += sum over inside cells of K_K u_K (sum factorised, one launch per colour)
+hipError_t launch_cell_apply(const DevPlan &p, const double *u, double *y, hipStream_t s);
+hipError_t launch_cell_apply_f32(const DevPlan &p, const float *u, float *y, hipStream_t s);
 // single-face microbenchmark: out = reps * G_F in per face, local layout [normal node][tangential line]
 hipError_t launch_face_micro(const DevPlan &p, const double *in, double *out, int64_t n_faces, int reps,
                              hipStream_t s);

@@ -1066,6 +1066,137 @@ hipError_t run_faces_marked(const DevPlan &p, const T *x, const T *u2, T *y, con
 
 }  // namespace
 
+// Interior-cell Laplacian (the cell term of the weak form, §2.1, on the cells the boundary does not cut,
+// evaluated by sum factorisation as in §2.5 and Algorithm 1): y += sum over inside cells K of K_K u_K with
+//   K_K = h^{d-2} sum_a (A on axis a, M on the others),
+// A and M the reference 1D stiffness and mass matrices.  One tangential x-line of a cell per lane (the
+// face kernel's lane layout with the normal along x), 64 / (k+1)^(d-1) cells per wavefront; the x factors
+// act within the lane, the y and z factors by rows in the wave's LDS, as in the face's mass passes:
+//   3D: P = M_y (A_x u) + A_y (M_x u), Q = M_y (M_x u), result = M_z P + A_z Q;
+//   2D: result = M_y (A_x u) + A_y (M_x u).
+// The cells of one launch share no node (one parity colour), so y is read, added to and written back.
+template <typename T, int D, int K>
+__global__ __launch_bounds__(kBoxThreads) void cell_kernel(const T *__restrict__ u, T *__restrict__ y,
+                                                           const int64_t *__restrict__ base, int64_t n_cells,
+                                                           int s1, int s2, T scale) {
+  constexpr int TL = D == 3 ? K * K : K, FW = 64 / TL, CPB = (kBoxThreads / 64) * FW;
+  using Tab = gen::Tab1d<K>;
+  __shared__ T sp[CPB * K * TL], sq[CPB * K * TL];  // per cell: [x][t], t = t1 + K t2
+  const int tid = threadIdx.x, lane_w = tid & 63, fw = lane_w / TL;
+  const int c = (tid >> 6) * FW + fw, t = lane_w - fw * TL;
+  const bool in_block = fw < FW;
+  const int t1 = (D == 3) ? t % K : t;
+  const int t2 = (D == 3) ? t / K : 0;
+  const int64_t cell = (int64_t)blockIdx.x * CPB + c;
+  const bool live = in_block && cell < n_cells;
+  const int64_t line0 = live ? base[cell] + (int64_t)s1 * t1 + (int64_t)s2 * t2 : 0;
+  T ul[K];
+#pragma unroll
+  for (int x = 0; x < K; ++x) ul[x] = live ? u[line0 + x] : T(0);
+  // x factors within the lane
+  T mx[K], ax[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    T m = T(0), a = T(0);
+#pragma unroll
+    for (int x = 0; x < K; ++x) {
+      m = fma(T(Tab::M[q * K + x]), ul[x], m);
+      a = fma(T(Tab::A[q * K + x]), ul[x], a);
+    }
+    mx[q] = m;
+    ax[q] = a;
+  }
+  T *P = &sp[c * K * TL], *Q = &sq[c * K * TL];
+  if (in_block) {
+#pragma unroll
+    for (int x = 0; x < K; ++x) {
+      P[x * TL + t] = ax[x];
+      Q[x * TL + t] = mx[x];
+    }
+  }
+  wave_sync();
+  // y factors: the lane owns row (x = t1, z = t2) of both arrays, K values along y
+  if (in_block) {
+    const int row = t1 * TL + K * t2;  // element y of the row at row + y
+    T pa[K], qm[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      pa[m] = P[row + m];
+      qm[m] = Q[row + m];
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      T sP = T(0), sQ = T(0);
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        sP = fma(T(Tab::M[q * K + m]), pa[m], sP);
+        sP = fma(T(Tab::A[q * K + m]), qm[m], sP);
+        sQ = fma(T(Tab::M[q * K + m]), qm[m], sQ);
+      }
+      P[row + q] = sP;
+      if (D == 3) Q[row + q] = sQ;
+    }
+  }
+  wave_sync();
+  if (D == 3) {
+    // z factors: the lane owns row (x = t2, y = t1), K values along z at stride K
+    if (in_block) {
+      const int row = t2 * TL + t1;
+      T pa[K], qm[K];
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        pa[m] = P[row + m * K];
+        qm[m] = Q[row + m * K];
+      }
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        T sR = T(0);
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+          sR = fma(T(Tab::M[q * K + m]), pa[m], sR);
+          sR = fma(T(Tab::A[q * K + m]), qm[m], sR);
+        }
+        P[row + q * K] = sR;
+      }
+    }
+    wave_sync();
+  }
+  if (live) {
+#pragma unroll
+    for (int x = 0; x < K; ++x) y[line0 + x] += scale * P[x * TL + t];
+  }
+}
+
+template <typename T>
+hipError_t launch_cell_apply_t(const DevPlan &p, const T *u, T *y, hipStream_t s) {
+  const T scale = (T)(p.dim == 3 ? p.h : 1.0);  // h^{d-2}
+  hipError_t e = hipSuccess;
+  for (int col = 0; col < (1 << p.dim) && e == hipSuccess; ++col) {
+    const int64_t b0 = p.inside_colour_begin[col], n = p.inside_colour_begin[col + 1] - b0;
+    if (n == 0) continue;
+    e = hipErrorInvalidValue;
+#define GHOST_CCASE(D_, K_)                                                                               \
+  if (p.dim == D_ && p.k + 1 == K_) {                                                                      \
+    constexpr int64_t cpb = (kBoxThreads / 64) * (64 / (D_ == 3 ? K_ * K_ : K_));                          \
+    hipLaunchKernelGGL((cell_kernel<T, D_, K_>), dim3((unsigned)((n + cpb - 1) / cpb)), dim3(kBoxThreads),  \
+                       0, s, u, y, p.inside_base + b0, n, p.stride[1], p.stride[2], scale);                \
+    e = hipGetLastError();                                                                                 \
+  }
+    GHOST_CCASE(2, 2) GHOST_CCASE(2, 3) GHOST_CCASE(2, 4) GHOST_CCASE(2, 5) GHOST_CCASE(2, 6) GHOST_CCASE(2, 7)
+    GHOST_CCASE(2, 8) GHOST_CCASE(3, 2) GHOST_CCASE(3, 3) GHOST_CCASE(3, 4) GHOST_CCASE(3, 5) GHOST_CCASE(3, 6)
+    GHOST_CCASE(3, 7) GHOST_CCASE(3, 8)
+#undef GHOST_CCASE
+  }
+  return e;
+}
+
+hipError_t launch_cell_apply(const DevPlan &p, const double *u, double *y, hipStream_t s) {
+  return launch_cell_apply_t<double>(p, u, y, s);
+}
+hipError_t launch_cell_apply_f32(const DevPlan &p, const float *u, float *y, hipStream_t s) {
+  return launch_cell_apply_t<float>(p, u, y, s);
+}
+
 // Single-face microbenchmark, compute-bound (the computational-efficiency experiment of §3, ghost
 // penalty only): every wave slot applies its face's operator to the same patch values `reps` times with
 // the box kernel's per-face pipeline (the values are made opaque to the compiler before each repetition,

@@ -231,6 +231,27 @@ void tables_1d(int k, std::vector<ld> &nodes, std::vector<ld> &weights, std::vec
                                  raw[(k - b) * K + (k - a)]);
 }
 
+void stiffness_1d(int k, std::vector<ld> &stiff) {
+  const int K = k + 1;
+  std::vector<ld> nodes, weights, jumps, mass;
+  tables_1d(k, nodes, weights, jumps, mass);
+  std::vector<ld> gx, gw;
+  gauss_pm1(K, gx, gw);
+  std::vector<ld> raw((size_t)K * K, 0);
+  for (int q = 0; q < K; ++q) {
+    const ld xq = (gx[q] + 1) / 2, wq = gw[q] / 2;
+    std::vector<ld> d1(K);
+    for (int a = 0; a < K; ++a) d1[a] = lagrange_derivs_at(nodes, a, xq)[1];
+    for (int a = 0; a < K; ++a)
+      for (int b = 0; b < K; ++b) raw[a * K + b] += wq * d1[a] * d1[b];
+  }
+  stiff.assign((size_t)K * K, 0);
+  for (int a = 0; a < K; ++a)
+    for (int b = 0; b < K; ++b)
+      stiff[a * K + b] = 0.25L * (raw[a * K + b] + raw[b * K + a] + raw[(k - a) * K + (k - b)] +
+                                  raw[(k - b) * K + (k - a)]);
+}
+
 std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], double h, int k,
                        int ls_kind, const double centre[3], double radius,
                        const signed char *cell_class, int n_balls, const double *balls, bool coloured) {
@@ -441,6 +462,43 @@ std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], dou
         }
       }
     merge_runs(iv, p.L[0], p.active_runs, p.n_active);
+  }
+  // ---- inside cells by parity colour
+  {
+    std::vector<std::vector<int64_t>> byc(1 << dim);
+    for (int c2 = 0; c2 < p.n[2]; ++c2)
+      for (int c1 = 0; c1 < p.n[1]; ++c1)
+        for (int c0 = 0; c0 < p.n[0]; ++c0)
+          if (cls_at(c0, c1, c2) == GHOST_INSIDE) {
+            const int col = (c0 & 1) + (dim >= 2 ? 2 * (c1 & 1) : 0) + (dim >= 3 ? 4 * (c2 & 1) : 0);
+            byc[col].push_back((int64_t)k * c0 + p.stride[1] * ((int64_t)k * c1) + p.stride[2] * ((int64_t)k * c2));
+          }
+    p.inside_base.clear();
+    for (int col = 0; col <= 8; ++col) p.inside_colour_begin[col] = 0;
+    for (int col = 0; col < (1 << dim); ++col) {
+      p.inside_colour_begin[col] = (int64_t)p.inside_base.size();
+      p.inside_base.insert(p.inside_base.end(), byc[col].begin(), byc[col].end());
+    }
+    for (int col = 1 << dim; col <= 8; ++col) p.inside_colour_begin[col] = (int64_t)p.inside_base.size();
+    // their distinct nodes, counted through x-runs as for the active nodes
+    std::vector<Interval> iv;
+    for (int c2 = 0; c2 < p.n[2]; ++c2)
+      for (int c1 = 0; c1 < p.n[1]; ++c1) {
+        int c0 = 0;
+        while (c0 < p.n[0]) {
+          if (cls_at(c0, c1, c2) != GHOST_INSIDE) { ++c0; continue; }
+          int e0 = c0;
+          while (e0 < p.n[0] && cls_at(e0, c1, c2) == GHOST_INSIDE) ++e0;
+          int64_t e1 = dim >= 2 ? k + 1 : 1, e2 = dim >= 3 ? k + 1 : 1;
+          for (int64_t i2 = 0; i2 < e2; ++i2)
+            for (int64_t i1 = 0; i1 < e1; ++i1)
+              iv.push_back({((int64_t)k * c1 + i1) + p.L[1] * ((int64_t)k * c2 + i2),
+                            (int64_t)k * c0, (int64_t)k * e0 + 1});
+          c0 = e0;
+        }
+      }
+    std::vector<Run> runs;
+    merge_runs(iv, p.L[0], runs, p.n_inside);
   }
 
   // ---- box layout for the default scatter

@@ -103,6 +103,12 @@ struct Plan {
   std::vector<Run> active_runs;        // nodes of active cells
   int64_t n_active = 0;
 
+  // inside cells (the interior Laplacian): lattice index of each cell's first node, grouped by colour
+  // (c0 mod 2) + 2 (c1 mod 2) + 4 (c2 mod 2), so that no two cells of a colour share a node
+  std::vector<int64_t> inside_base;
+  int64_t n_inside = 0;  // distinct nodes of the inside cells
+  int64_t inside_colour_begin[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+
   // 1D tables, rounded from long double
   std::vector<double> jumps;   // k x (2k+1)
   std::vector<double> mass;    // (k+1) x (k+1)
@@ -117,6 +123,10 @@ std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], dou
 
 // Box layout (see Box).  Called by build_plan.
 std::string build_box_layout(Plan &p);
+
+// Reference 1D stiffness on [0, 1], A[a][b] = integral of l_a' l_b' ((k+1)-point Gauss, exact), made
+// exactly symmetric and centro-symmetric; for the interior-cell Laplacian.
+void stiffness_1d(int k, std::vector<long double> &stiff);
 
 // 1D tables in extended precision (exposed for the host tests through the ABI).
 void tables_1d(int k, std::vector<long double> &nodes, std::vector<long double> &weights,

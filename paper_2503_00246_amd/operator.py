@@ -122,6 +122,21 @@ class GhostOperator:
         L.check(self._lib.ghost_apply(self._h, _ptr(u), _ptr(y), int(accumulate), _stream(self._dev())))
         return y
 
+    def cell_apply(self, u, y=None):
+        """y += K_inside u: the Laplacian on the cells the boundary does not cut (float64 or float32,
+        y allocated zeroed when omitted)."""
+        import torch
+        dt = u.dtype if isinstance(u, torch.Tensor) else None
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("u must be a float64 or float32 torch tensor")
+        self._vec(u, dt, "u")
+        if y is None:
+            y = torch.zeros_like(u)
+        self._vec(y, dt, "y")
+        fn = self._lib.ghost_cell_apply if dt == torch.float64 else self._lib.ghost_cell_apply_f32
+        L.check(fn(self._h, _ptr(u), _ptr(y), _stream(self._dev())))
+        return y
+
     def face_bench(self, inp, out=None, reps=1):
         """Single-face microbenchmark: out = reps * G_F inp for every face of inp, a float64 or float32
         CUDA tensor of shape (n_faces, 2k+1, (k+1)^(d-1)) in the face's local layout [normal node][line]."""

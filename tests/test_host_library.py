@@ -121,6 +121,9 @@ def test_plan_matches_oracle(name):
     sup = np.unique(np.concatenate([omesh.patch_dofs(faces[a], w.k, a, L_).ravel() for a in range(w.d)]))
     assert st["n_support_dofs"] == len(sup)
     assert st["bytes_fp64"] == 24 * len(sup)
+    from oracle.cell import cell_dofs
+    inside = np.argwhere(cls == omesh.INSIDE)
+    assert st["n_inside_dofs"] == (len(np.unique(cell_dofs(inside, w.k, w.lattice))) if len(inside) else 0)
     if w.d == 2:
         o = GhostOracle(w.d, w.n, w.lo, w.h, w.k, w.gamma(), centre=w.centre, radius=w.radius)
         assert st["n_active_dofs"] == int(np.sum(o.lumped_mass() > 0))
