@@ -16,6 +16,8 @@ Modules
   basis     1D nodes, Lagrange polynomials, quadrature (mpmath, 60 digits)
   mesh      cell classification, ghost-face set, lattice numbering
   patch     dense two-cell patch matrix of one face, by quadrature
+  macro     dense patch matrix of the macro-patch stabilisation, by quadrature
+  cell      dense cell stiffness and the Laplacian on the inside cells
   operator  global apply, sparse assembly, gradients, lumped mass, CG
 
 Parity status: every function is pinned by the CPU tests (closed forms,
@@ -23,4 +25,4 @@ invariants, brute force); none is "parity unpinned" except the CG solution
 vector beyond its residual (see cg_reference).
 """
 
-from . import basis, mesh, patch, operator  # noqa: F401
+from . import basis, mesh, patch, macro, operator, cell  # noqa: F401

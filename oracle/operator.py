@@ -10,6 +10,9 @@
 * Gradients of L = 0.5 |G(gamma) u - t|^2: dL/du = G^T (G u - t),
   dL/dgamma_j = (G u - t)^T G_j u, with G_j the operator for gamma = e_j
   (G is linear in gamma, §2.4 eq. ghostPenaltyMatrixRev).
+* penalty="macro": the macro-patch stabilisation of macro.macro_patch_matrix in place of the
+  derivative-jump penalty, with one coefficient gamma_M (G is linear in it, so its gradient is
+  (G u - t)^T G_1 u with G_1 the operator for gamma_M = 1).
 * Lumped mass for the linear-solver workload: diagonal GLL mass of the
   active cells, M_ii = sum over active cells K containing node i of
   h^d prod_a w_{i_a}.
@@ -21,6 +24,7 @@ import scipy.sparse as sp
 
 from . import mesh
 from .patch import patch_matrix
+from .macro import macro_patch_matrix
 from .basis import gll_weights
 
 
@@ -28,9 +32,15 @@ class GhostOracle:
     """Ghost-penalty operator on a Cartesian mesh with a ball, a union of balls, or given cell classes."""
 
     def __init__(self, d, n, lo, h, k, gamma, centre=None, radius=None, cell_class=None,
-                 per_face=False, check_faces=8, seed=0, balls=None):
+                 per_face=False, check_faces=8, seed=0, balls=None, penalty="derivative"):
         self.d, self.n, self.lo, self.h, self.k = d, tuple(n), tuple(lo), float(h), k
+        if penalty not in ("derivative", "macro"):
+            raise ValueError("penalty must be 'derivative' or 'macro'")
+        self.penalty = penalty
+        self.n_gamma = k if penalty == "derivative" else 1
         self.gamma = np.asarray(gamma, dtype=np.float64)
+        if self.gamma.shape != (self.n_gamma,):
+            raise ValueError(f"need {self.n_gamma} coefficients")
         if balls:
             self.cls = mesh.classify_balls(self.n, self.lo, self.h, balls)
         elif cell_class is None:
@@ -64,6 +74,8 @@ class GhostOracle:
     # ------------------------------------------------------------------ assembly
     def _assemble(self, axis, lower_cell, gamma=None):
         g = self.gamma if gamma is None else gamma
+        if self.penalty == "macro":
+            return macro_patch_matrix(self.d, self.k, axis, lower_cell, self.lo, self.h, g)
         return patch_matrix(self.d, self.k, axis, lower_cell, self.lo, self.h, g)
 
     def n_faces(self):
@@ -145,10 +157,10 @@ class GhostOracle:
                              shape=(self.n_lattice, self.n_lattice)).tocsr()
 
     def order_matrices(self):
-        """G_j for j = 1..k (gamma = e_j)."""
+        """G_j = dG/dgamma_j for each coefficient (gamma = e_j)."""
         out = []
-        for j in range(self.k):
-            e = np.zeros(self.k)
+        for j in range(self.n_gamma):
+            e = np.zeros(self.n_gamma)
             e[j] = 1.0
             out.append(self.sparse(gamma=e))
         return out
