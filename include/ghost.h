@@ -65,6 +65,15 @@ extern "C" {
 #define GHOST_FP32 2u
 #define GHOST_COLOURED 4u /* scatter strategy: face-parallel, plain read-modify-write per race-free colour */
 #define GHOST_ATOMIC 8u   /* scatter strategy: face-parallel, hardware FP64/FP32 atomics */
+/* Macro-patch stabilisation (§2.2, the alternative to the derivative jumps with the same tensor-product
+ * structure) in place of the ghost penalty:
+ *   u^T S v = sum_{F in F_h} gamma_M h^-2 integral over the patch K_1 u K_2 of F of
+ *             (E_1 u - E_2 u)(E_1 v - E_2 v),
+ * E_i u the polynomial extension of u restricted to cell K_i.  One coefficient gamma_M (gamma, set_gamma
+ * and the VJP's dgamma then have length 1).  Applied in the same rank-k form, with the k derivative
+ * orders coupled by a fixed k x k matrix.  Box scatter only: not combinable with GHOST_COLOURED or
+ * GHOST_ATOMIC. */
+#define GHOST_MACRO_PATCH 16u
 /* With neither flag the default box scatter is used: the cells are cut into bricks; a workgroup
  * applies every face with a cell in its brick (expanding only into the brick's cells), sums the
  * contributions over the brick's node box in LDS, writes nodes no other box contains straight to y
@@ -116,6 +125,8 @@ typedef struct {
   double bytes_fp64;          /* compulsory bytes of an accumulating FP64 apply: 24 per support DoF */
   double bytes_fp32;          /* same for FP32: 12 per support DoF */
   int64_t n_inside_dofs;      /* nodes of inside cells (the interior Laplacian's nodes) */
+  int n_gamma;                /* coefficients of the penalty: k, or 1 with GHOST_MACRO_PATCH */
+  int macro;                  /* 1 for a GHOST_MACRO_PATCH context */
 } ghost_stats;
 
 /*
@@ -124,12 +135,14 @@ typedef struct {
  * (jump vectors of the two-cell patch and the reference mass matrix, §2.4) in
  * extended precision, and upload everything to `device`.
  *   k       polynomial degree, 1..GHOST_KMAX
- *   gamma   HOST array of k coefficients gamma_1..gamma_k, finite and >= 0
+ *   gamma   HOST array of k coefficients gamma_1..gamma_k, finite and >= 0 (one, gamma_M, with
+ *           GHOST_MACRO_PATCH)
  *   device  HIP device ordinal, or -1 for a host-only plan (no GPU touched; only
  *           ghost_info / ghost_faces / ghost_tables / ghost_destroy are valid on it)
  *   out     receives the new context (owned by the caller; free with ghost_destroy)
  * Errors: GHOST_EINVAL (null pointer, dim not 2/3, n < 2, h <= 0, k out of range,
- * bad gamma, bad level set, lattice above 2^31 nodes per axis plane), GHOST_ENOMEM,
+ * bad gamma, bad level set, lattice above 2^31 nodes per axis plane, unknown flags,
+ * GHOST_MACRO_PATCH with a face-parallel scatter), GHOST_ENOMEM,
  * GHOST_EHIP.  On error nothing is leaked and *out is left NULL.
  */
 int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const double *gamma,
@@ -138,8 +151,9 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
 /*
  * Replace gamma (G is linear in gamma, §2.4 summed-penalty equation).  Stream-ordered:
  * applies enqueued later on `stream` see the new values.
- *   gamma_on_device = 0: HOST array of k doubles, validated (finite, >= 0).
- *   gamma_on_device = 1: DEVICE array of k doubles, read by a kernel on `stream`;
+ *   gamma_on_device = 0: HOST array of n_gamma doubles (k, or 1 with GHOST_MACRO_PATCH),
+ *                        validated (finite, >= 0).
+ *   gamma_on_device = 1: DEVICE array of n_gamma doubles, read by a kernel on `stream`;
  *                        not validated.
  */
 int ghost_set_gamma(ghost_ctx *ctx, const double *gamma, int gamma_on_device, void *stream);
@@ -159,7 +173,8 @@ int ghost_apply_f32(ghost_ctx *ctx, const float *u, float *y, int accumulate, vo
 /*
  * Pull-back of a cotangent w on y = G(gamma) u (G symmetric, linear in gamma):
  *   du (+)= G w            (DEVICE, n_lattice doubles; accumulate_du as in ghost_apply)
- *   dgamma[j] = w^T G_j u  (DEVICE, k doubles, overwritten), G_j = dG/dgamma_j.
+ *   dgamma[j] = w^T G_j u  (DEVICE, n_gamma doubles, overwritten), G_j = dG/dgamma_j
+ *                          (with GHOST_MACRO_PATCH: one value, w^T S u / gamma_M evaluated as such).
  * dgamma is reduced deterministically (fixed order, no atomics).  u, w, du must not
  * overlap du.
  */
@@ -177,7 +192,8 @@ int ghost_mass_diag(ghost_ctx *ctx, double *diag, void *stream);
 /*
  * diag (+)= the diagonal of G (§2.4: for a patch node at normal position i and tangential
  * positions t, sum_j gamma_j h^{d-1-2j} g_j[i]^2 times the diagonal mass entries), summed over
- * the faces, for the current gamma.  diag: DEVICE array of n_lattice doubles; accumulate = 0 zeroes
+ * the faces, for the current gamma; with GHOST_MACRO_PATCH, gamma_M h^{d-2} sum_ab H_ab g_a[i] g_b[i]
+ * with the order coupling H.  diag: DEVICE array of n_lattice doubles; accumulate = 0 zeroes
  * the support first (other entries untouched).  Stream-ordered; uses FP64 atomics (meant for
  * preconditioner set-up, not for the hot loop).
  */
@@ -204,6 +220,7 @@ int ghost_cell_apply_f32(ghost_ctx *ctx, const float *u, float *y, void *stream)
  * normal axis).  in, out: DEVICE arrays of n_faces * (2k+1) * (k+1)^(d-1) values in the layout
  * [face][normal node i = 0..2k][tangential line t], t = t1 + (k+1) t2 with t1, t2 along the tangential
  * axes in increasing order; out is overwritten.  n_faces >= 0, reps >= 1.  Stream-ordered.
+ * GHOST_ESTATE for a GHOST_MACRO_PATCH context (derivative-jump form only).
  */
 int ghost_face_bench(ghost_ctx *ctx, const double *in, double *out, int64_t n_faces, int reps, void *stream);
 int ghost_face_bench_f32(ghost_ctx *ctx, const float *in, float *out, int64_t n_faces, int reps, void *stream);

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libghost.so
 GHOST_OK, GHOST_EINVAL, GHOST_ENOMEM, GHOST_EHIP, GHOST_ESTATE = 0, -1, -2, -3, -4
 GHOST_KMAX = 7
 GHOST_LS_BALL, GHOST_LS_CELLS, GHOST_LS_BALLS = 0, 1, 2
-GHOST_FP64, GHOST_FP32, GHOST_COLOURED, GHOST_ATOMIC = 1, 2, 4, 8
+GHOST_FP64, GHOST_FP32, GHOST_COLOURED, GHOST_ATOMIC, GHOST_MACRO_PATCH = 1, 2, 4, 8, 16
 GHOST_CG_FP64, GHOST_CG_MIXED = 0, 1
 GHOST_CG_NONE, GHOST_CG_JACOBI = 0, 1
 
@@ -43,7 +43,8 @@ class GhostStats(ctypes.Structure):
                 ("n_boxes", ctypes.c_int64), ("n_visits", ctypes.c_int64), ("n_halo_slots", ctypes.c_int64),
                 ("n_halo_nodes", ctypes.c_int64), ("brick", ctypes.c_int),
                 ("flops_per_face", ctypes.c_double), ("bytes_fp64", ctypes.c_double),
-                ("bytes_fp32", ctypes.c_double), ("n_inside_dofs", ctypes.c_int64)]
+                ("bytes_fp32", ctypes.c_double), ("n_inside_dofs", ctypes.c_int64),
+                ("n_gamma", ctypes.c_int), ("macro", ctypes.c_int)]
 
     def as_dict(self):
         out = {}

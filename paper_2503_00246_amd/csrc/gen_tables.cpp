@@ -1,8 +1,9 @@
 // Build-time generator of the 1D tables as compile-time constants for the box kernel:
 //   gen_tables OUT.h
 // writes, for every degree k = 1..kMaxDegree, the reference jump vectors (k x (2k+1), row j-1 = order
-// j), the reference mass matrix ((k+1) x (k+1)) and the reference stiffness matrix (the interior-cell
-// Laplacian's 1D factor), computed by tables_1d / stiffness_1d in long double and rounded
+// j), the reference mass matrix ((k+1) x (k+1)), the reference stiffness matrix (the interior-cell
+// Laplacian's 1D factor) and the order coupling H of the macro-patch form (k x k), computed by
+// tables_1d / stiffness_1d / macro_mix_1d in long double and rounded
 // once to double, as hexadecimal floating literals (exact).  The kernels fold them into immediates,
 // so the face pipeline reads no table from memory.
 #include <cstdio>
@@ -31,6 +32,10 @@ int main(int argc, char **argv) {
     ghost::stiffness_1d(k, stiff);
     std::fprintf(f, "};\n  static constexpr double A[%zu] = {", stiff.size());
     for (size_t i = 0; i < stiff.size(); ++i) std::fprintf(f, "%s%a", i ? ", " : "", (double)stiff[i]);
+    std::vector<long double> mix;
+    ghost::macro_mix_1d(k, mix);
+    std::fprintf(f, "};\n  static constexpr double H[%zu] = {", mix.size());
+    for (size_t i = 0; i < mix.size(); ++i) std::fprintf(f, "%s%a", i ? ", " : "", (double)mix[i]);
     std::fprintf(f, "};\n};\n\n");
   }
   std::fprintf(f, "}  // namespace gen\n}  // namespace ghost\n");

@@ -111,18 +111,22 @@ void host_tables(const ghost_ctx *c, std::vector<double> &t64, std::vector<float
   const int k = p.k, NN = 2 * k + 1, K = k + 1;
   t64.assign(ghost::tab_size64(k), 0.0);
   t32.assign(ghost::tab_size32(k), 0.0f);
-  for (int j = 0; j < k; ++j) {
-    const long double hs = powl((long double)p.h, (long double)(p.dim - 1 - 2 * (j + 1)));
-    t64[ghost::tab_hscale(k) + j] = (double)hs;
+  // h-power of each coefficient: h^{d-1-2j} for order j (derivative form), h^{d-2} for gamma_M (the
+  // patch integral of h^{-2} times the extension difference, h^d times its reference value)
+  const int ng = c->dev.n_gamma;
+  for (int j = 0; j < ng; ++j) {
+    const int e = c->dev.macro ? p.dim - 2 : p.dim - 1 - 2 * (j + 1);
+    t64[ghost::tab_hscale(k) + j] = (double)powl((long double)p.h, (long double)e);
   }
   for (int i = 0; i < k * NN; ++i) {
     const int j = i / NN;
     t64[i] = p.jumps[i];
-    t64[ghost::tab_gs(k) + i] = (c->gamma[j] * t64[ghost::tab_hscale(k) + j]) * p.jumps[i];
+    if (j < ng) t64[ghost::tab_gs(k) + i] = (c->gamma[j] * t64[ghost::tab_hscale(k) + j]) * p.jumps[i];
   }
-  for (int j = 0; j < k; ++j) t64[ghost::tab_coef(k) + j] = c->gamma[j] * t64[ghost::tab_hscale(k) + j];
+  for (int j = 0; j < ng; ++j) t64[ghost::tab_coef(k) + j] = c->gamma[j] * t64[ghost::tab_hscale(k) + j];
   for (int i = 0; i < K * K; ++i) t64[ghost::tab_M(k) + i] = p.mass[i];
   for (int i = 0; i < K; ++i) t64[ghost::tab_gllw(k) + i] = p.weights[i];
+  for (int i = 0; i < k * k; ++i) t64[ghost::tab_mix(k) + i] = p.mix[i];
   for (int i = 0; i < ghost::tab_size32(k); ++i) t32[i] = (float)t64[i];
 }
 
@@ -165,7 +169,9 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
     if (!std::isfinite(mesh->lo[a])) return fail(GHOST_EINVAL, "lo must be finite");
   }
   if (!(mesh->h > 0) || !std::isfinite(mesh->h)) return fail(GHOST_EINVAL, "h must be positive and finite");
-  if (!finite_nonneg(gamma, k)) return fail(GHOST_EINVAL, "gamma must be finite and >= 0");
+  const bool macro = (flags & GHOST_MACRO_PATCH) != 0;
+  const int n_gamma = macro ? 1 : k;
+  if (!finite_nonneg(gamma, n_gamma)) return fail(GHOST_EINVAL, "gamma must be finite and >= 0");
   if (ls->kind == GHOST_LS_BALL) {
     if (!(ls->radius > 0) || !std::isfinite(ls->radius)) return fail(GHOST_EINVAL, "radius must be positive");
     for (int a = 0; a < mesh->dim; ++a)
@@ -183,15 +189,18 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
   } else {
     return fail(GHOST_EINVAL, "unknown level-set kind %d", ls->kind);
   }
-  if (flags & ~(GHOST_FP64 | GHOST_FP32 | GHOST_COLOURED | GHOST_ATOMIC)) return fail(GHOST_EINVAL, "unknown flags");
+  if (flags & ~(GHOST_FP64 | GHOST_FP32 | GHOST_COLOURED | GHOST_ATOMIC | GHOST_MACRO_PATCH))
+    return fail(GHOST_EINVAL, "unknown flags");
   if ((flags & GHOST_COLOURED) && (flags & GHOST_ATOMIC))
     return fail(GHOST_EINVAL, "GHOST_COLOURED and GHOST_ATOMIC are exclusive");
+  if (macro && (flags & (GHOST_COLOURED | GHOST_ATOMIC)))
+    return fail(GHOST_EINVAL, "GHOST_MACRO_PATCH runs on the box scatter only (no GHOST_COLOURED / GHOST_ATOMIC)");
   if (device < -1) return fail(GHOST_EINVAL, "device must be >= -1");
 
   ghost_ctx *c = new (std::nothrow) ghost_ctx;
   if (!c) return fail(GHOST_ENOMEM, "out of host memory");
   try {
-    c->gamma.assign(gamma, gamma + k);
+    c->gamma.assign(gamma, gamma + n_gamma);
     std::string err = ghost::build_plan(c->plan, mesh->dim, mesh->n, mesh->lo, mesh->h, k, ls->kind,
                                         ls->centre, ls->radius, ls->cell_class, ls->n_balls, ls->balls,
                                         (flags & GHOST_COLOURED) != 0);
@@ -211,6 +220,8 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
   ghost::DevPlan &d = c->dev;
   d.dim = p.dim;
   d.k = p.k;
+  d.macro = macro;
+  d.n_gamma = n_gamma;
   d.h = p.h;
   for (int a = 0; a < 3; ++a) {
     d.stride[a] = (int32_t)p.stride[a];
@@ -323,10 +334,11 @@ int ghost_set_gamma(ghost_ctx *ctx, const double *gamma, int gamma_on_device, vo
   if (gamma_on_device) {
     e = ghost::launch_set_gamma(ctx->dev, gamma, static_cast<hipStream_t>(stream));
   } else {
-    if (!finite_nonneg(gamma, ctx->plan.k)) return fail(GHOST_EINVAL, "gamma must be finite and >= 0");
-    ctx->gamma.assign(gamma, gamma + ctx->plan.k);
+    const int ng = ctx->dev.n_gamma;
+    if (!finite_nonneg(gamma, ng)) return fail(GHOST_EINVAL, "gamma must be finite and >= 0");
+    ctx->gamma.assign(gamma, gamma + ng);
     ghost::GammaArg arg{};
-    for (int j = 0; j < ctx->plan.k; ++j) arg.v[j] = gamma[j];
+    for (int j = 0; j < ng; ++j) arg.v[j] = gamma[j];
     e = ghost::launch_set_gamma_host(ctx->dev, arg, static_cast<hipStream_t>(stream));
   }
   return e == hipSuccess ? GHOST_OK : fail_hip(e, "set_gamma launch");
@@ -434,6 +446,7 @@ int face_bench(ghost_ctx *ctx, const T *in, T *out, int64_t n_faces, int reps, v
   if (!ctx || (n_faces > 0 && (!in || !out))) return fail(GHOST_EINVAL, "null context, in or out");
   if (ctx->device < 0) return fail(GHOST_ESTATE, "host-only context");
   if (n_faces < 0 || reps < 1) return fail(GHOST_EINVAL, "need n_faces >= 0 and reps >= 1");
+  if (ctx->dev.macro) return fail(GHOST_ESTATE, "the face microbenchmark runs the derivative-jump form only");
   int64_t n_p = 2 * ctx->plan.k + 1;
   for (int a = 1; a < ctx->plan.dim; ++a) n_p *= ctx->plan.k + 1;
   if (n_faces > ((int64_t)1 << 40) / n_p) return fail(GHOST_EINVAL, "n_faces too large");
@@ -504,6 +517,8 @@ int ghost_info(const ghost_ctx *ctx, ghost_stats *out) {
   out->n_active_dofs = p.n_active;
   out->n_support_dofs = p.n_support;
   out->n_inside_dofs = p.n_inside;
+  out->n_gamma = ctx->dev.n_gamma;
+  out->macro = ctx->dev.macro ? 1 : 0;
   const int K = p.k + 1;
   int64_t tang = 1;
   for (int a = 1; a < p.dim; ++a) tang *= K;

@@ -14,13 +14,17 @@ namespace ghost {
 //   [k*NN, 2*k*NN)       gs   : gamma_j h^{d-1-2j} g_j, the expansion coefficients of one face
 //   [2*k*NN, +K*K)       M    : reference mass matrix
 //   [.., +k)             coef : gamma_j h^{d-1-2j}
-//   FP64 buffer only: [.., +k) hscale_j = h^{d-1-2j}, then [.., +K) GLL weights on [0, 1]
+//   FP64 buffer only: [.., +k) hscale_j = h^{d-1-2j}, then [.., +K) GLL weights on [0, 1], then
+//   [.., +k*k) the order coupling H of the macro-patch form
+// Macro-patch contexts have one coefficient gamma_M: coef_0 = gamma_M h^{d-2}, hscale_0 = h^{d-2}, the
+// other coef / hscale entries and the gs rows past the first are zero.
 __host__ __device__ constexpr int tab_gs(int k) { return k * (2 * k + 1); }
 __host__ __device__ constexpr int tab_M(int k) { return 2 * k * (2 * k + 1); }
 __host__ __device__ constexpr int tab_coef(int k) { return tab_M(k) + (k + 1) * (k + 1); }
 __host__ __device__ constexpr int tab_hscale(int k) { return tab_coef(k) + k; }
 __host__ __device__ constexpr int tab_gllw(int k) { return tab_hscale(k) + k; }
-__host__ __device__ constexpr int tab_size64(int k) { return tab_gllw(k) + k + 1; }
+__host__ __device__ constexpr int tab_mix(int k) { return tab_gllw(k) + k + 1; }
+__host__ __device__ constexpr int tab_size64(int k) { return tab_mix(k) + k * k; }
 __host__ __device__ constexpr int tab_size32(int k) { return tab_hscale(k); }
 
 enum class Scatter { Box = 0, Atomic = 1, Coloured = 2 };
@@ -34,6 +38,8 @@ struct BoxSched {
 
 struct DevPlan {
   int dim = 0, k = 0;
+  bool macro = false;  // macro-patch stabilisation in place of the derivative-jump penalty
+  int n_gamma = 0;     // coefficients: k (derivative form) or 1 (macro-patch form)
   Scatter scatter = Scatter::Box;
   int32_t stride[3] = {1, 1, 1};
   int n[3] = {1, 1, 1};

@@ -490,15 +490,28 @@ __device__ __forceinline__ void face_masses(T *sa, int f, int t, int t1, int t2,
   }
 }
 
+// Order coupling of the macro-patch form: m_i = sum_j H[i][j] c_j, H zero for i + j odd.
 template <typename T, int K>
-__device__ __forceinline__ void face_expand(const T (&cj)[K - 1], const T (&coef)[K - 1], T (&yv2)[2 * K - 1]) {
+__device__ __forceinline__ void macro_mix(const T (&cj)[K - 1], T (&m)[K - 1]) {
+  constexpr int k = K - 1;
+  using Tab = gen::Tab1d<K>;
+#pragma unroll
+  for (int i = 0; i < k; ++i) {
+    T s = T(0);
+#pragma unroll
+    for (int j = i % 2; j < k; j += 2) s = fma(T(Tab::H[i * k + j]), cj[j], s);
+    m[i] = s;
+  }
+}
+
+// Expansion onto the patch line from the scaled order values cs_j (derivative form: coef_j c_j with
+// coef_j = gamma_j h^{d-1-2j}; macro-patch form: gamma_M h^{d-2} m_j).
+template <typename T, int K>
+__device__ __forceinline__ void face_expand(const T (&cs)[K - 1], T (&yv2)[2 * K - 1]) {
   constexpr int k = K - 1, NN = 2 * k + 1;
   using Tab = gen::Tab1d<K>;
-  // expansion y_i = sum_j coef_j g_j[i] c_j (coef_j = gamma_j h^{d-1-2j}), folded: E_i from the
-  // symmetric orders, O_i from the others, y_i = E_i + O_i and y_{2k-i} = E_i - O_i
-  T cs[k];
-#pragma unroll
-  for (int j = 0; j < k; ++j) cs[j] = coef[j] * cj[j];
+  // y_i = sum_j g_j[i] cs_j, folded: E_i from the symmetric orders, O_i from the others,
+  // y_i = E_i + O_i and y_{2k-i} = E_i - O_i
 #pragma unroll
   for (int i = 0; i <= k; ++i) {
     T e = T(0), o = T(0);
@@ -550,7 +563,9 @@ __device__ __forceinline__ void decode_lines(const BoxLine *slines, int grp, Lin
 // issued before the flush of this one.
 // VJP: x = w drives du; u2 = u gives the order-wise reduction, counted on each face's primary visit,
 // and stored per box so that the reduction order does not depend on the schedule.
-template <typename T, int D, int K, bool VJP>
+// MACRO: the macro-patch stabilisation, whose orders are coupled by H before the expansion (and whose
+// one coefficient's reduction pairs u's orders with the coupled w values).
+template <typename T, int D, int K, bool VJP, bool MACRO>
 __device__ __forceinline__ void box_body(
     const T *__restrict__ x, const T *__restrict__ u2, T *__restrict__ y, T *__restrict__ halo,
     double *__restrict__ partial, const Box *__restrict__ boxes, const Visit *__restrict__ visits,
@@ -704,8 +719,28 @@ __device__ __forceinline__ void box_body(
 #pragma unroll
       for (int j = 0; j < k; ++j) cj[j] = in_block ? sa[(f * k + j) * TL + t] : T(0);
       if (cur_p.live) {
+        T cs[k];
+        if (MACRO) {
+          T hm[k];
+          macro_mix<T, K>(cj, hm);
+#pragma unroll
+          for (int j = 0; j < k; ++j) cs[j] = coef[0] * hm[j];
+          if (VJP && cur_p.prim) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < k; ++j) s += (double)au[j] * (double)hm[j];
+            pj[0] += s;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < k; ++j) cs[j] = coef[j] * cj[j];
+          if (VJP && cur_p.prim) {
+#pragma unroll
+            for (int j = 0; j < k; ++j) pj[j] += (double)au[j] * (double)cj[j];
+          }
+        }
         T yv2[NN];
-        face_expand<T, K>(cj, coef, yv2);
+        face_expand<T, K>(cs, yv2);
         if (cur_p.lo) {
           int off = cur_p.acc0;
 #pragma unroll
@@ -717,10 +752,6 @@ __device__ __forceinline__ void box_body(
 #pragma unroll
           for (int i = k + 1; i < NN; ++i, off += cur_p.dacc)
             acc_add(&acc[off], (A)yv2[i]);
-        }
-        if (VJP && cur_p.prim) {
-#pragma unroll
-          for (int j = 0; j < k; ++j) pj[j] += (double)au[j] * (double)cj[j];
         }
       }
       wave_sync();  // sa is reused by this wave's next round
@@ -816,15 +847,15 @@ __device__ __forceinline__ void box_body(
 // that for the apply (FP32 at every degree and FP64 up to k = 6 fit without spilling).  The VJP and the
 // FP64 apply at k = 7 carry more live values and run one block per CU instead: spilled values reloaded
 // behind a gather would make the flush wait for it.
-template <typename T, int D, int K, bool VJP>
+template <typename T, int D, int K, bool VJP, bool MACRO>
 __global__ __launch_bounds__(kBoxThreads) __attribute__((amdgpu_waves_per_eu(4))) void box_kernel(
     GHOST_BOX_PARAMS) {
-  box_body<T, D, K, VJP>(GHOST_BOX_ARGS);
+  box_body<T, D, K, VJP, MACRO>(GHOST_BOX_ARGS);
 }
 
-template <typename T, int D, int K, bool VJP>
+template <typename T, int D, int K, bool VJP, bool MACRO>
 __global__ __launch_bounds__(kBoxThreads) void box_kernel_wide(GHOST_BOX_PARAMS) {
-  box_body<T, D, K, VJP>(GHOST_BOX_ARGS);
+  box_body<T, D, K, VJP, MACRO>(GHOST_BOX_ARGS);
 }
 #undef GHOST_BOX_PARAMS
 #undef GHOST_BOX_ARGS
@@ -873,32 +904,34 @@ __global__ void vjp_reduce_kernel(const double *__restrict__ partial, int n_batc
   if (tid == 0) dgamma[j] = hscale[j] * red[0];
 }
 
-// gs_j = gamma_j * hscale_j * g_j and coef_j = gamma_j * hscale_j in FP64, and their FP32 roundings.
-__device__ void write_gamma_tables(const double *gamma, int k, double *__restrict__ tab64,
+// gs_j = gamma_j * hscale_j * g_j and coef_j = gamma_j * hscale_j in FP64, and their FP32 roundings,
+// for the ng coefficients of the context (k, or 1 for the macro-patch form).
+__device__ void write_gamma_tables(const double *gamma, int ng, int k, double *__restrict__ tab64,
                                    float *__restrict__ tab32) {
   const int NN = 2 * k + 1;
   const double *hscale = tab64 + tab_hscale(k);
-  for (int idx = threadIdx.x; idx < k * NN; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < ng * NN; idx += blockDim.x) {
     const int j = idx / NN;
     const double v = (gamma[j] * hscale[j]) * tab64[idx];
     tab64[k * NN + idx] = v;
     tab32[k * NN + idx] = (float)v;
   }
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+  for (int j = threadIdx.x; j < ng; j += blockDim.x) {
     const double c = gamma[j] * hscale[j];
     tab64[tab_coef(k) + j] = c;
     tab32[tab_coef(k) + j] = (float)c;
   }
 }
 
-__global__ void set_gamma_kernel(const double *__restrict__ gamma, int k, double *__restrict__ tab64,
+__global__ void set_gamma_kernel(const double *__restrict__ gamma, int ng, int k, double *__restrict__ tab64,
                                  float *__restrict__ tab32) {
-  write_gamma_tables(gamma, k, tab64, tab32);
+  write_gamma_tables(gamma, ng, k, tab64, tab32);
 }
 
 // Same, with gamma passed by value from the host.
-__global__ void set_gamma_host_kernel(GammaArg g, int k, double *__restrict__ tab64, float *__restrict__ tab32) {
-  write_gamma_tables(g.v, k, tab64, tab32);
+__global__ void set_gamma_host_kernel(GammaArg g, int ng, int k, double *__restrict__ tab64,
+                                      float *__restrict__ tab32) {
+  write_gamma_tables(g.v, ng, k, tab64, tab32);
 }
 
 __global__ void fill_kernel(double *__restrict__ y, int64_t n, double v) {
@@ -969,7 +1002,7 @@ hipError_t dispatch(const DevPlan &p, const T *x, const T *u2, T *y, double *par
 }
 
 
-template <typename T, int D, int K, bool VJP>
+template <typename T, int D, int K, bool VJP, bool MACRO>
 void launch_box(const DevPlan &p, const T *x, const T *u2, T *y, T *halo, const T *tab, bool accumulate,
                 hipStream_t s) {
   // persistent workgroups: as many as fit on the device at once (the first launch asks the runtime)
@@ -977,9 +1010,9 @@ void launch_box(const DevPlan &p, const T *x, const T *u2, T *y, T *halo, const 
   // the VJP and the FP64 apply at k = 7 hold too many live values for 128 VGPRs: one block per CU
   constexpr bool kWide = VJP || (sizeof(T) == 8 && K == 8);
   if constexpr (kWide)
-    fn = reinterpret_cast<const void *>(&box_kernel_wide<T, D, K, VJP>);
+    fn = reinterpret_cast<const void *>(&box_kernel_wide<T, D, K, VJP, MACRO>);
   else
-    fn = reinterpret_cast<const void *>(&box_kernel<T, D, K, VJP>);
+    fn = reinterpret_cast<const void *>(&box_kernel<T, D, K, VJP, MACRO>);
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
@@ -989,10 +1022,10 @@ void launch_box(const DevPlan &p, const T *x, const T *u2, T *y, T *halo, const 
   const int resident = per_cu * (p.n_cu > 0 ? p.n_cu : 1);
   const dim3 grid(p.n_boxes < resident ? p.n_boxes : resident), block(kBoxThreads);
   if constexpr (kWide)
-    hipLaunchKernelGGL((box_kernel_wide<T, D, K, VJP>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes,
+    hipLaunchKernelGGL((box_kernel_wide<T, D, K, VJP, MACRO>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes,
                        p.visits, p.box_lines, tab, p.stride[1], p.stride[2], (int)accumulate, p.n_boxes, p.sched);
   else
-    hipLaunchKernelGGL((box_kernel<T, D, K, VJP>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes,
+    hipLaunchKernelGGL((box_kernel<T, D, K, VJP, MACRO>), grid, block, 0, s, x, u2, y, halo, p.vjp_partial, p.boxes,
                        p.visits, p.box_lines, tab, p.stride[1], p.stride[2], (int)accumulate, p.n_boxes, p.sched);
 }
 
@@ -1014,7 +1047,10 @@ hipError_t dispatch_box(const DevPlan &p, const T *x, const T *u2, T *y, const T
   hipError_t e = hipErrorInvalidValue;
 #define GHOST_BCASE(D_, K_)                                           \
   if (p.dim == D_ && p.k + 1 == K_) {                                 \
-    launch_box<T, D_, K_, VJP>(p, x, u2, y, halo, tab, accumulate, s); \
+    if (p.macro)                                                      \
+      launch_box<T, D_, K_, VJP, true>(p, x, u2, y, halo, tab, accumulate, s); \
+    else                                                              \
+      launch_box<T, D_, K_, VJP, false>(p, x, u2, y, halo, tab, accumulate, s); \
     e = hipGetLastError();                                            \
   }
   GHOST_BCASE(2, 2) GHOST_BCASE(2, 3) GHOST_BCASE(2, 4) GHOST_BCASE(2, 5) GHOST_BCASE(2, 6) GHOST_BCASE(2, 7)
@@ -1239,8 +1275,10 @@ __global__ __launch_bounds__(kBoxThreads) void face_micro_kernel(const T *__rest
     T cj[k];
 #pragma unroll
     for (int j = 0; j < k; ++j) cj[j] = in_block ? sa[(f * k + j) * TL + t] : T(0);
-    T yv2[NN];
-    face_expand<T, K>(cj, coef, yv2);
+    T cs[k], yv2[NN];
+#pragma unroll
+    for (int j = 0; j < k; ++j) cs[j] = coef[j] * cj[j];
+    face_expand<T, K>(cs, yv2);
 #pragma unroll
     for (int i = 0; i < NN; ++i) acc[i] += yv2[i];
     wave_sync();  // sa is rewritten by the next repetition
@@ -1310,31 +1348,33 @@ hipError_t launch_vjp(const DevPlan &p, const double *u, const double *w, double
   }
   if (e != hipSuccess) return e;
   if (n_parts == 0) {
-    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, dgamma, (int64_t)p.k, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, dgamma, (int64_t)p.n_gamma, 0.0);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(vjp_reduce_kernel, dim3(p.k), dim3(kBlockThreads), 0, s, p.vjp_partial, n_parts,
+  // partial holds k values per box or batch; the first n_gamma are reduced
+  hipLaunchKernelGGL(vjp_reduce_kernel, dim3(p.n_gamma), dim3(kBlockThreads), 0, s, p.vjp_partial, n_parts,
                      p.k, p.tab64 + tab_hscale(p.k), dgamma);
   return hipGetLastError();
 }
 
 hipError_t launch_set_gamma(const DevPlan &p, const double *gamma_dev, hipStream_t s) {
-  hipLaunchKernelGGL(set_gamma_kernel, dim3(1), dim3(128), 0, s, gamma_dev, p.k, p.tab64, p.tab32);
+  hipLaunchKernelGGL(set_gamma_kernel, dim3(1), dim3(128), 0, s, gamma_dev, p.n_gamma, p.k, p.tab64, p.tab32);
   return hipGetLastError();
 }
 
 hipError_t launch_set_gamma_host(const DevPlan &p, GammaArg g, hipStream_t s) {
-  hipLaunchKernelGGL(set_gamma_host_kernel, dim3(1), dim3(128), 0, s, g, p.k, p.tab64, p.tab32);
+  hipLaunchKernelGGL(set_gamma_host_kernel, dim3(1), dim3(128), 0, s, g, p.n_gamma, p.k, p.tab64, p.tab32);
   return hipGetLastError();
 }
 
 // diag[node] += the diagonal of G at every patch node of every face: for the patch node at normal
 // position i and tangential positions (t1, t2), sum_j coef_j g_j[i]^2 M[t1][t1] M[t2][t2] (the
-// diagonal of the Kronecker factors, §2.4).  One workgroup per face batch; FP64 atomics (setup-time
-// use by the preconditioned CG).
+// diagonal of the Kronecker factors, §2.4); for the macro-patch form coef_0 sum_ab H[a][b] g_a[i] g_b[i]
+// in place of the sum.  One workgroup per face batch; FP64 atomics (setup-time use by the
+// preconditioned CG).
 __global__ void ghost_diag_kernel(double *__restrict__ diag, const int64_t *__restrict__ face_base,
                                   const Batch *__restrict__ batches, const double *__restrict__ tab, int dim, int k,
-                                  int s0, int s1, int s2) {
+                                  int macro, int s0, int s1, int s2) {
   const Batch bt = batches[blockIdx.x];
   const int K = k + 1, NN = 2 * k + 1;
   const int np = NN * K * (dim == 3 ? K : 1);
@@ -1347,7 +1387,14 @@ __global__ void ghost_diag_kernel(double *__restrict__ diag, const int64_t *__re
     const int f = idx / np, q = idx - f * np;
     const int i = q % NN, t = q / NN, t1 = t % K, t2 = t / K;
     double gi = 0.0;
-    for (int j = 0; j < k; ++j) gi += coef[j] * g[j * NN + i] * g[j * NN + i];
+    if (macro) {
+      const double *H = tab + tab_mix(k);
+      for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) gi += H[a * k + b] * g[a * NN + i] * g[b * NN + i];
+      gi *= coef[0];
+    } else {
+      for (int j = 0; j < k; ++j) gi += coef[j] * g[j * NN + i] * g[j * NN + i];
+    }
     const double v = gi * M[t1 * K + t1] * (dim == 3 ? M[t2 * K + t2] : 1.0);
     atomicAdd(&diag[face_base[bt.first + f] + (int64_t)i * sn + (int64_t)t1 * st1 + (int64_t)t2 * st2], v);
   }
@@ -1358,7 +1405,7 @@ hipError_t launch_zero_support(const DevPlan &p, double *y, hipStream_t s) { ret
 hipError_t launch_ghost_diag(const DevPlan &p, double *diag, hipStream_t s) {
   if (p.n_batches == 0) return hipSuccess;
   hipLaunchKernelGGL(ghost_diag_kernel, dim3(p.n_batches), dim3(kBlockThreads), 0, s, diag, p.face_base, p.batches,
-                     (const double *)p.tab64, p.dim, p.k, p.stride[0], p.stride[1], p.stride[2]);
+                     (const double *)p.tab64, p.dim, p.k, (int)p.macro, p.stride[0], p.stride[1], p.stride[2]);
   return hipGetLastError();
 }
 

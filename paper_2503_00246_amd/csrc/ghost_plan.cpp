@@ -252,6 +252,15 @@ void stiffness_1d(int k, std::vector<ld> &stiff) {
                                   raw[(k - b) * K + (k - a)]);
 }
 
+void macro_mix_1d(int k, std::vector<ld> &mix) {
+  std::vector<ld> fact(2 * k + 2, 1);
+  for (int i = 1; i < (int)fact.size(); ++i) fact[i] = fact[i - 1] * i;
+  mix.assign((size_t)k * k, 0);
+  for (int i = 1; i <= k; ++i)
+    for (int j = 1; j <= k; ++j)
+      if ((i + j) % 2 == 0) mix[(i - 1) * k + (j - 1)] = 2.0L / ((i + j + 1) * fact[i] * fact[j]);
+}
+
 std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], double h, int k,
                        int ls_kind, const double centre[3], double radius,
                        const signed char *cell_class, int n_balls, const double *balls, bool coloured) {
@@ -514,6 +523,9 @@ std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], dou
   p.weights.assign(wt.begin(), wt.end());
   p.jumps.assign(jp.begin(), jp.end());
   p.mass.assign(ms.begin(), ms.end());
+  std::vector<ld> mx;
+  macro_mix_1d(k, mx);
+  p.mix.assign(mx.begin(), mx.end());
   return "";
 }
 

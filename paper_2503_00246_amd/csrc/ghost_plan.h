@@ -114,6 +114,7 @@ struct Plan {
   std::vector<double> mass;    // (k+1) x (k+1)
   std::vector<double> nodes;   // k+1 GLL nodes on [0,1]
   std::vector<double> weights; // k+1 GLL weights on [0,1]
+  std::vector<double> mix;     // k x k order coupling of the macro-patch form
 };
 
 // Builds the plan; returns an empty string on success or an error message.
@@ -127,6 +128,15 @@ std::string build_box_layout(Plan &p);
 // Reference 1D stiffness on [0, 1], A[a][b] = integral of l_a' l_b' ((k+1)-point Gauss, exact), made
 // exactly symmetric and centro-symmetric; for the interior-cell Laplacian.
 void stiffness_1d(int k, std::vector<long double> &stiff);
+
+// Order coupling of the macro-patch stabilisation (§2.2, its alternative form), k x k, orders i, j =
+// 1..k: H[i][j] = integral over [-1, 1] of t^(i+j) dt / (i! j!), zero for i + j odd.  On the
+// reference patch (two unit cells, face at t = 0) the difference of the two cells' polynomial
+// extensions has degree k and vanishes at the face, and its Taylor coefficients about the face are
+// the derivative jumps g_j . u over j! (up to one sign, which cancels in products).  So the patch
+// integral of the product of two such differences is sum_ij (g_i . u) H[i][j] (g_j . v): the rank-k
+// penalty with a k x k coupling of the orders in place of a diagonal.
+void macro_mix_1d(int k, std::vector<long double> &mix);
 
 // 1D tables in extended precision (exposed for the host tests through the ABI).
 void tables_1d(int k, std::vector<long double> &nodes, std::vector<long double> &weights,

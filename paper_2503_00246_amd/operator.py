@@ -24,16 +24,18 @@ class GhostOperator:
     """Matrix-free ghost penalty y = G(gamma) u on a Cartesian mesh cut by a level set.
 
     d, n, lo, h: mesh (cells per axis, lower corner, cell side); k: degree;
-    gamma: k coefficients; either (centre, radius) of a ball, balls (a sequence of
+    gamma: k coefficients (penalty="derivative", the ghost penalty of derivative jumps) or one,
+    gamma_M (penalty="macro", the macro-patch stabilisation); either (centre, radius) of a ball, balls (a sequence of
     (c0, c1, c2, r), their union), or cell_class (x-fastest array of 0 outside /
     1 inside / 2 cut).  device=-1 builds a
     host-only plan (inspection without a GPU).
     """
 
     SCATTERS = ("box", "atomic", "coloured")
+    PENALTIES = ("derivative", "macro")
 
     def __init__(self, d, n, lo, h, k, gamma, centre=None, radius=None, cell_class=None,
-                 scatter="box", device=0, balls=None):
+                 scatter="box", device=0, balls=None, penalty="derivative"):
         lib = L.load()
         mesh = L.GhostMesh()
         mesh.dim = d
@@ -59,11 +61,19 @@ class GhostOperator:
             for a in range(3):
                 ls.centre[a] = float(centre[a]) if a < d else 0.0
             ls.radius = float(radius)
-        g = (ctypes.c_double * k)(*[float(x) for x in gamma])
+        if penalty not in self.PENALTIES:
+            raise ValueError(f"penalty must be one of {self.PENALTIES}")
+        n_gamma = k if penalty == "derivative" else 1
+        gamma = [float(x) for x in gamma]
+        if len(gamma) != n_gamma:
+            raise ValueError(f"need {n_gamma} coefficients for the {penalty} penalty")
+        g = (ctypes.c_double * n_gamma)(*gamma)
         if scatter not in self.SCATTERS:
             raise ValueError(f"scatter must be one of {self.SCATTERS}")
         flags = L.GHOST_FP64 | L.GHOST_FP32 | {"box": 0, "atomic": L.GHOST_ATOMIC,
                                                "coloured": L.GHOST_COLOURED}[scatter]
+        if penalty == "macro":
+            flags |= L.GHOST_MACRO_PATCH
         self.scatter = scatter
         handle = ctypes.c_void_p()
         L.check(lib.ghost_setup(ctypes.byref(mesh), ctypes.byref(ls), int(k), g, flags, int(device),
@@ -71,17 +81,19 @@ class GhostOperator:
         self._h = handle
         self._lib = lib
         self.d, self.k, self.device = d, k, device
-        self.gamma = [float(x) for x in gamma]
+        self.penalty, self.n_gamma = penalty, n_gamma
+        self.gamma = gamma
         st = L.GhostStats()
         L.check(lib.ghost_info(self._h, ctypes.byref(st)))
         self.stats = st.as_dict()
         self.n_lattice = self.stats["n_lattice"]
 
     @classmethod
-    def from_workload(cls, w, scatter="box", device=0, gamma=None):
-        return cls(w.d, w.n, w.lo, w.h, w.k, w.gamma() if gamma is None else gamma,
-                   centre=w.centre, radius=w.radius, scatter=scatter, device=device,
-                   balls=w.balls if w.balls else None)
+    def from_workload(cls, w, scatter="box", device=0, gamma=None, penalty="derivative"):
+        if gamma is None:
+            gamma = w.gamma() if penalty == "derivative" else [w.gamma_macro()]
+        return cls(w.d, w.n, w.lo, w.h, w.k, gamma, centre=w.centre, radius=w.radius, scatter=scatter,
+                   device=device, balls=w.balls if w.balls else None, penalty=penalty)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -173,23 +185,24 @@ class GhostOperator:
         if du is None:
             du = torch.zeros_like(u)
         self._vec(du, torch.float64, "du")
-        dg = torch.empty(self.k, dtype=torch.float64, device=self._dev())
+        dg = torch.empty(self.n_gamma, dtype=torch.float64, device=self._dev())
         L.check(self._lib.ghost_vjp(self._h, _ptr(u), _ptr(w), _ptr(du), _ptr(dg), int(accumulate),
                                     _stream(self._dev())))
         return du, dg
 
     def set_gamma(self, gamma):
-        """Replace gamma: a host sequence (validated) or a float64 CUDA tensor of k values (stream-ordered)."""
+        """Replace gamma: a host sequence (validated) or a float64 CUDA tensor of n_gamma values
+        (stream-ordered)."""
         import torch
         if isinstance(gamma, torch.Tensor) and gamma.device.type == "cuda":
-            if gamma.dtype != torch.float64 or gamma.numel() != self.k or not gamma.is_contiguous():
-                raise ValueError("device gamma must be a contiguous float64 tensor of k values")
+            if gamma.dtype != torch.float64 or gamma.numel() != self.n_gamma or not gamma.is_contiguous():
+                raise ValueError(f"device gamma must be a contiguous float64 tensor of {self.n_gamma} values")
             L.check(self._lib.ghost_set_gamma(self._h, _ptr(gamma), 1, _stream(self._dev())))
             return
         vals = [float(x) for x in (gamma.tolist() if hasattr(gamma, "tolist") else gamma)]
-        if len(vals) != self.k:
-            raise ValueError("need k coefficients")
-        arr = (ctypes.c_double * self.k)(*vals)
+        if len(vals) != self.n_gamma:
+            raise ValueError(f"need {self.n_gamma} coefficients")
+        arr = (ctypes.c_double * self.n_gamma)(*vals)
         L.check(self._lib.ghost_set_gamma(self._h, ctypes.cast(arr, ctypes.c_void_p), 0, _stream(self._dev())))
         self.gamma = vals
 

@@ -48,6 +48,13 @@ class Workload:
     def gamma(self):
         return gamma_paper(self.k, self.h)
 
+    def gamma_macro(self):
+        """gamma_M of the macro-patch stabilisation: the paper's gamma_A = 0.5 (its h-scaling is in the form)."""
+        return GAMMA_MACRO
+
+
+GAMMA_MACRO = 0.5
+
 
 def gamma_paper(k, h, gamma_a=0.5):
     return [gamma_a * h ** (2 * j - 1) / math.factorial(j) ** 2 for j in range(1, k + 1)]

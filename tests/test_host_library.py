@@ -222,6 +222,50 @@ def test_setup_rejects_bad_balls(balls, needle):
                       device=-1)
 
 
+@pytest.mark.parametrize("kw,needle", [
+    (dict(flags=L.GHOST_MACRO_PATCH | L.GHOST_ATOMIC, gamma=(1.0,)), "box scatter"),
+    (dict(flags=L.GHOST_MACRO_PATCH | L.GHOST_COLOURED, gamma=(1.0,)), "box scatter"),
+    (dict(flags=L.GHOST_MACRO_PATCH, gamma=(-1.0,)), "gamma"),
+    (dict(flags=L.GHOST_MACRO_PATCH, gamma=(float("nan"),)), "gamma"),
+])
+def test_macro_setup_rejections(lib, kw, needle):
+    rc, msg = _raw_setup(lib, **kw)
+    assert rc == L.GHOST_EINVAL and needle in msg, msg
+
+
+def test_macro_context_stats():
+    w = WORKLOADS["disk2d_q2_32"]
+    m = GhostOperator.from_workload(w, device=-1, penalty="macro")
+    assert m.stats["macro"] == 1 and m.stats["n_gamma"] == 1 and m.n_gamma == 1
+    g = GhostOperator.from_workload(w, device=-1)
+    assert g.stats["macro"] == 0 and g.stats["n_gamma"] == w.k
+    for key in ("n_faces_total", "n_support_dofs", "n_boxes"):
+        assert m.stats[key] == g.stats[key]
+    with pytest.raises(ValueError):
+        GhostOperator.from_workload(w, device=-1, penalty="macro", gamma=[1.0, 1.0])
+    with pytest.raises(ValueError):
+        GhostOperator.from_workload(w, device=-1, penalty="jump")
+
+
+def test_generated_macro_coupling_reproduces_oracle():
+    """The kernels' compile-time order coupling H with the library's jump vectors g gives g^T H g, which
+    must equal the oracle's 1D macro-patch matrix on the reference patch (assembled from the extension
+    differences by quadrature, without derivatives): a check of the Taylor-coefficient derivation."""
+    from oracle.macro import macro_matrix_1d
+    text = open(os.path.join(ROOT, "_build", "ghost_tables_gen.h")).read()
+    blocks = dict(re.findall(r"struct Tab1d<(\d+)> \{[^}]*\};[^}]*\};[^}]*\};\s*"
+                             r"static constexpr double H\[\d+\] = \{([^}]*)\};", text))
+    assert sorted(int(K) for K in blocks) == list(range(2, 9))
+    w = WORKLOADS["disk2d_q2_32"]
+    for K, H in blocks.items():
+        k = int(K) - 1
+        op = GhostOperator(2, w.n, w.lo, w.h, k, gamma_paper(k, w.h), centre=w.centre, radius=w.radius, device=-1)
+        g = np.asarray(op.tables()["jumps"]).reshape(k, 2 * k + 1)
+        Hm = np.array([float.fromhex(x.strip()) for x in H.split(",")]).reshape(k, k)
+        ref = macro_matrix_1d(k, 0.0, 1.0)
+        assert np.max(np.abs(g.T @ Hm @ g - ref)) <= 1e-12 * np.max(np.abs(ref)), k
+
+
 def test_bad_cell_class_value(lib):
     cls = (ctypes.c_byte * 64)(*([0] * 63 + [5]))
     rc, msg = _raw_setup(lib, kind=1, cls=ctypes.cast(cls, ctypes.POINTER(ctypes.c_byte)))
