@@ -52,12 +52,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="one JSON line per degree/mesh of the roofline sweep")
-    ap.add_argument("--mode", default="apply", choices=["apply", "vjp", "cg", "balls", "micro", "cell"],
+    ap.add_argument("--mode", default="apply", choices=["apply", "vjp", "cg", "balls", "micro", "cell", "macro"],
                     help="apply: the benchmark line; vjp: ghost_vjp on ball3d_q4_96; cg: FP64 vs mixed CG on "
                          "ball3d_q7_96; balls: the multiple-ball problem, throughput against the cut fraction; "
                          "micro: the single-face compute-bound microbenchmark, d = 2, 3 and k = 1..7; "
-                         "cell: the interior-cell Laplacian and (K_inside + G) u on the workload "
-                         "(extra lines, not the benchmark metric)")
+                         "cell: the interior-cell Laplacian and (K_inside + G) u on the workload; "
+                         "macro: the macro-patch stabilisation against the derivative form, k = 3..7, and its "
+                         "VJP (extra lines, not the benchmark metric)")
     ap.add_argument("--balls-k", type=int, default=3, help="degree of the multiple-ball problem")
     ap.add_argument("--balls-n", type=int, default=128, help="cells per axis of the multiple-ball problem")
     ap.add_argument("--cg-max-iter", type=int, default=5000)
@@ -147,13 +148,13 @@ def graph_time(fn, steps, repeats=10):
     return statistics.median(times)
 
 
-def run_workload(w, args, with_cpu):
+def run_workload(w, args, with_cpu, penalty="derivative"):
     import numpy as np
     import torch
     from paper_2503_00246_amd.operator import GhostOperator
     from paper_2503_00246_amd.workloads import SEED_U, uniform_vector
 
-    op = GhostOperator.from_workload(w, scatter=args.scatter)
+    op = GhostOperator.from_workload(w, scatter=args.scatter, penalty=penalty)
     st = op.stats
     u_np = uniform_vector(w.n_lattice, SEED_U)
     u = torch.from_numpy(u_np).cuda()
@@ -200,14 +201,14 @@ def run_workload(w, args, with_cpu):
     return out
 
 
-def run_vjp(w, args):
+def run_vjp(w, args, penalty="derivative"):
     """ghost_vjp (du = G w and dgamma) timed like the apply; box-kernel bytes: u and w read on the
     support, du written on the exclusive nodes (overwrite mode)."""
     import torch
     from paper_2503_00246_amd.operator import GhostOperator
     from paper_2503_00246_amd.workloads import SEED_T, SEED_U, uniform_vector
 
-    op = GhostOperator.from_workload(w, scatter=args.scatter)
+    op = GhostOperator.from_workload(w, scatter=args.scatter, penalty=penalty)
     st = op.stats
     u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda()
     wv = torch.from_numpy(uniform_vector(w.n_lattice, SEED_T)).cuda()
@@ -224,7 +225,7 @@ def run_vjp(w, args):
     kt = op.kernel_times()
     box_t = kt["main_ms"] / 1e3 / kt["calls"]
     alg = 24 * st["n_support_dofs"]  # u and w read, du written on the support
-    print(json.dumps({"metric": "ghost_vjp patch DoFs/s (GDoF/s), FP64", "workload": w.name,
+    print(json.dumps({"metric": "ghost_vjp patch DoFs/s (GDoF/s), FP64", "workload": w.name, "penalty": penalty,
                       "value": round(st["n_faces_total"] * st["n_patch_dofs"] / t / 1e9, 4), "unit": "GDoF/s",
                       "ms_per_step": round(t * 1e3, 5), "steps": args.steps,
                       "box_kernel_us": round(box_t * 1e6, 2), "halo_pass_us": round(kt["halo_ms"] / kt["calls"] * 1e3, 2),
@@ -353,6 +354,31 @@ def run_balls(args):
               flush=True)
 
 
+def run_macro(args):
+    """The macro-patch stabilisation against the derivative-jump penalty on the same meshes: one line per
+    degree, both forms timed like the apply (the same box layout, bytes and faces; the macro form adds
+    the k x k order coupling per tangential line)."""
+    from paper_2503_00246_amd.workloads import sweep_workload
+    args.sweep = True  # one line per workload: no overwrite or graph timings
+    for k, n in [(3, 128), (4, 96), (5, 128), (6, 96), (7, 96)]:
+        w = sweep_workload(k, n)
+        line = {"metric": "ghost-face patch DoFs/s (GDoF/s), macro-patch vs derivative-jump form",
+                "workload": w.name}
+        for pen in ("macro", "derivative"):
+            r = run_workload(w, args, with_cpu=False, penalty=pen)
+            st = r["stats"]
+            line[pen] = {"ms64": round(r["t64"] * 1e3, 5), "gdofs64": round(r["gdofs64"], 2),
+                         "box_ms64": round(r["box64"] * 1e3, 5),
+                         "box_frac64": round(box_bytes(st, 8) / r["box64"] / 1e9 / HBM_PEAK_GBS, 4),
+                         "ms32": round(r.get("t32", 0) * 1e3, 5), "gdofs32": round(r.get("gdofs32", 0), 2),
+                         "err32": r.get("err32")}
+        line["faces"], line["n_p"] = st["n_faces_total"], st["n_patch_dofs"]
+        print(json.dumps(line), flush=True)
+    from paper_2503_00246_amd.workloads import WORKLOADS
+    for pen in ("macro", "derivative"):
+        run_vjp(WORKLOADS["ball3d_q4_96"], args, penalty=pen)
+
+
 def box_bytes(st, elem):
     """Algorithmic bytes of one accumulating box-kernel launch: u on the support, and y read and written
     on the support (every support node is written to y by exactly one box, the first that touches it;
@@ -383,6 +409,9 @@ def main():
         return
     if args.mode == "cell":
         run_cell(WORKLOADS[args.workload], args)
+        return
+    if args.mode == "macro":
+        run_macro(args)
         return
     if args.sweep:
         for k, n in [(3, 128), (3, 96), (4, 96), (5, 96), (5, 128), (6, 96), (7, 96)]:
