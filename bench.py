@@ -194,6 +194,12 @@ def run_workload(w, args, with_cpu, penalty="derivative"):
         c.copy_(u)  # one plain copy: n_lattice * 8 bytes read and written
         torch.cuda.synchronize()
         out["copy_bytes"] = 8 * w.n_lattice
+    if not args.sweep:
+        # a plain device copy of u (read and write of the whole lattice), for the attainable HBM rate
+        c = torch.empty_like(u)
+        t_copy = timed_applies(lambda: c.copy_(u), 20, 3)
+        out["copy_GBps"] = 2 * 8 * w.n_lattice / t_copy / 1e9
+        del c
     if with_cpu:
         out["cpu"] = cpu_baseline(w, u_np)
     del u, y
@@ -460,6 +466,8 @@ def main():
                      "traffic": traffic, "bytes_per_launch": box_bytes(st, 8),
                      "avg_launch_us": round(r["box64"] * 1e6, 2), "halo_pass_us": round(r["halo64"] * 1e6, 2)},
         "apply_roofline_frac": round(st["bytes_fp64"] / r["t64"] / 1e9 / HBM_PEAK_GBS, 4),
+        # a plain device copy of the lattice vector on the same GPU: the HBM rate a streaming kernel attains
+        "copy_GBps": round(r["copy_GBps"], 1),
         # faces x patch DoFs x 24 B per apply time: the traffic the per-face patches would move without
         # any reuse between overlapping patches
         "patch_traffic_GBps": round(r["gdofs64"] * 24, 1),

@@ -252,7 +252,9 @@ typedef struct {
  * Solve (M + G) x = b from x = 0.  b, x: DEVICE arrays of n_lattice doubles; b must be
  * zero on inactive nodes.  x is written on the active nodes only; its other entries are
  * left as they were.  Synchronous: returns when the solve ends.  Allocates its workspace
- * on the first call (kept until ghost_destroy).
+ * on the first call (kept until ghost_destroy).  The host reads the recursive residual of the
+ * unpreconditioned and the inner FP32 iterations every 8 iterations, so a solve may run up to 7
+ * iterations past the point where it would have stopped.
  */
 int ghost_cg(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts *opts,
              ghost_cg_result *res, void *stream);

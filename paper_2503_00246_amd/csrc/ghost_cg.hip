@@ -15,6 +15,8 @@
 //
 // Vectors live on the lattice; kernels visit only the active nodes, cut into segments
 // of at most 256 consecutive nodes (one wavefront each, 4 nodes per lane).
+// The host reads the recursive residual every kPoll iterations only, so that the stream is not drained
+// every iteration (a solve may run up to kPoll - 1 iterations past its recursive stopping point).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,6 +28,7 @@ namespace ghost {
 
 namespace {
 constexpr int kSegLen = 256;
+constexpr int kPoll = 8;
 constexpr int kSegPerBlock = kBlockThreads / 64;
 enum { S_RR = 0, S_PQ, S_ALPHA, S_BETA, S_TMP, S_COUNT = 8 };
 
@@ -387,11 +390,12 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
       R.reduce(2);
       update_p = true;
       ++it;
-      if (!jac) {
+      const bool poll = !jac && (it % kPoll == 0 || it >= opts.max_iter);
+      if (poll) {
         rr = R.read(S_RR);  // without a preconditioner <r, z> = |r|^2: test the recursive residual
         rr_true = rr;
       }
-      if ((!jac && std::sqrt(rr) <= target) || it % every == 0) {
+      if ((poll && std::sqrt(rr) <= target) || it % every == 0) {
         // replace the recursive residual by the true one (the search direction is kept)
         rr_true = R.true_residual(b, x, w->r, dinv);
       }
@@ -426,8 +430,10 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
         R.reduce(2);
         update_p = true;
         ++it;
-        rr = R.read(S_RR);
-        if (!std::isfinite(rr)) break;
+        if (it % kPoll == 0 || it >= opts.max_iter) {
+          rr = R.read(S_RR);
+          if (!std::isfinite(rr)) break;
+        }
       }
       hipLaunchKernelGGL(add_kernel, grid, block, 0, s, w->segs, w->n_segs, x, (const float *)w->e32, 0);
       R.check();
