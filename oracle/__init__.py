@@ -12,6 +12,12 @@ physical coordinates.  It does NOT use the Kronecker factorisation of §2.4 or
 the sum-factorised three-step apply of §2.5.1; those are what the GPU path
 implements and what the oracle checks.
 
+Two further operators are checked the same way, each from its own definition:
+  * the macro-patch stabilisation, the alternative form named in §2.2: the patch integral of the
+    difference of the two cells' polynomial extensions (macro.py);
+  * the Laplacian on the cells the boundary does not cut: the cell term of §2.1, with the dense cell
+    stiffness by quadrature (cell.py).
+
 Modules
   basis     1D nodes, Lagrange polynomials, quadrature (mpmath, 60 digits)
   mesh      cell classification, ghost-face set, lattice numbering
