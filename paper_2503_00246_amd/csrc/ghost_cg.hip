@@ -14,7 +14,9 @@
 // FP64 dot products and scalars, run until its residual drops by inner_tol.
 //
 // Vectors live on the lattice; kernels visit only the active nodes, cut into segments
-// of at most 256 consecutive nodes (one wavefront each, 4 nodes per lane).
+// of at most 256 consecutive nodes.  Each wavefront takes segments in a grid-stride loop over a
+// grid capped at kMaxBlocks workgroups (enough to fill the device), so that a dot product leaves at
+// most kMaxBlocks partial sums for its one-block reduction.
 // The host reads the recursive residual every kPoll iterations only, so that the stream is not drained
 // every iteration (a solve may run up to kPoll - 1 iterations past its recursive stopping point).
 #include <hip/hip_runtime.h>
@@ -30,6 +32,7 @@ namespace {
 constexpr int kSegLen = 256;
 constexpr int kPoll = 8;
 constexpr int kSegPerBlock = kBlockThreads / 64;
+constexpr int kMaxBlocks = 2048;
 enum { S_RR = 0, S_PQ, S_ALPHA, S_BETA, S_TMP, S_COUNT = 8 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -53,12 +56,15 @@ __device__ __forceinline__ void block_partial(double v, double *partial) {
   }
 }
 
-#define SEG_LOOP                                                     \
-  const int seg = blockIdx.x * kSegPerBlock + (threadIdx.x >> 6);     \
-  const int lane = threadIdx.x & 63;                                  \
-  Run sg{0, 0, 0};                                                    \
-  if (seg < n_segs) sg = segs[seg];                                   \
-  for (int i = lane; i < sg.len; i += 64)
+// f(j) for every active node j; the wave's lanes take consecutive nodes of a segment.
+template <typename F>
+__device__ __forceinline__ void for_active(const Run *__restrict__ segs, int n_segs, F f) {
+  const int lane = threadIdx.x & 63;
+  for (int seg = blockIdx.x * kSegPerBlock + (threadIdx.x >> 6); seg < n_segs; seg += gridDim.x * kSegPerBlock) {
+    const Run sg = segs[seg];
+    for (int i = lane; i < sg.len; i += 64) f(sg.start + i);
+  }
+}
 
 // With a preconditioner, z = dinv * r (Jacobi); without one (dinv null), z = r.
 template <typename T>
@@ -71,15 +77,14 @@ template <typename T>
 __global__ void start_kernel(const Run *segs, int n_segs, const double *src, T *x, T *r, T *p, const T *dinv,
                              double *partial) {
   double acc = 0.0;
-  SEG_LOOP {
-    const int64_t j = sg.start + i;
+  for_active(segs, n_segs, [&](int64_t j) {
     const T v = (T)src[j];
     const T z = precond(dinv, j, v);
     x[j] = T(0);
     r[j] = v;
     p[j] = z;
     acc += (double)v * (double)z;
-  }
+  });
   block_partial(acc, partial);
 }
 
@@ -88,24 +93,22 @@ template <typename T>
 __global__ void pq_kernel(const Run *segs, int n_segs, T *p, const T *r, T *q, const T *mdiag, const T *dinv,
                           const double *scal, int update_p) {
   const T beta = (T)scal[S_BETA];
-  SEG_LOOP {
-    const int64_t j = sg.start + i;
+  for_active(segs, n_segs, [&](int64_t j) {
     T pv = p[j];
     if (update_p) {
       pv = precond(dinv, j, r[j]) + beta * pv;
       p[j] = pv;
     }
     q[j] = mdiag[j] * pv;
-  }
+  });
 }
 
 template <typename T>
 __global__ void dot_kernel(const Run *segs, int n_segs, const T *a, const T *b, double *partial) {
   double acc = 0.0;
-  SEG_LOOP {
-    const int64_t j = sg.start + i;
+  for_active(segs, n_segs, [&](int64_t j) {
     acc += (double)a[j] * (double)b[j];
-  }
+  });
   block_partial(acc, partial);
 }
 
@@ -115,70 +118,63 @@ __global__ void xr_kernel(const Run *segs, int n_segs, T *x, T *r, const T *p, c
                           const double *scal, double *partial) {
   const T alpha = (T)scal[S_ALPHA];
   double acc = 0.0;
-  SEG_LOOP {
-    const int64_t j = sg.start + i;
+  for_active(segs, n_segs, [&](int64_t j) {
     x[j] += alpha * p[j];
     const T rv = r[j] - alpha * q[j];
     r[j] = rv;
     acc += (double)rv * (double)precond(dinv, j, rv);
-  }
+  });
   block_partial(acc, partial);
 }
 
 // partial <r, dinv r>
 __global__ void rz_kernel(const Run *segs, int n_segs, const double *r, const double *dinv, double *partial) {
   double acc = 0.0;
-  SEG_LOOP {
-    const int64_t j = sg.start + i;
+  for_active(segs, n_segs, [&](int64_t j) {
     acc += r[j] * dinv[j] * r[j];
-  }
+  });
   block_partial(acc, partial);
 }
 
 // d = 1 / d on the active nodes (the Jacobi preconditioner from the diagonal of A), and its FP32 copy
 __global__ void invert_kernel(const Run *segs, int n_segs, double *d, float *d32) {
-  SEG_LOOP {
-    const int64_t j = sg.start + i;
+  for_active(segs, n_segs, [&](int64_t j) {
     const double v = 1.0 / d[j];
     d[j] = v;
     d32[j] = (float)v;
-  }
+  });
 }
 
 // q = mdiag * x (FP64), the mass part of A x
 __global__ void mass_kernel(const Run *segs, int n_segs, const double *x, const double *mdiag, double *q) {
-  SEG_LOOP {
-    const int64_t j = sg.start + i;
+  for_active(segs, n_segs, [&](int64_t j) {
     q[j] = mdiag[j] * x[j];
-  }
+  });
 }
 
 // r = b - q; partial <r, r>
 __global__ void residual_kernel(const Run *segs, int n_segs, const double *b, const double *q, double *r,
                                 double *partial) {
   double acc = 0.0;
-  SEG_LOOP {
-    const int64_t j = sg.start + i;
+  for_active(segs, n_segs, [&](int64_t j) {
     const double v = b[j] - q[j];
     r[j] = v;
     acc += v * v;
-  }
+  });
   block_partial(acc, partial);
 }
 
 // x += (double) e; also zero x (init) when mode == 1
 __global__ void add_kernel(const Run *segs, int n_segs, double *x, const float *e, int zero) {
-  SEG_LOOP {
-    const int64_t j = sg.start + i;
+  for_active(segs, n_segs, [&](int64_t j) {
     x[j] = zero ? 0.0 : x[j] + (double)e[j];
-  }
+  });
 }
 
 __global__ void cast_kernel(const Run *segs, int n_segs, const double *a, float *b) {
-  SEG_LOOP {
-    const int64_t j = sg.start + i;
+  for_active(segs, n_segs, [&](int64_t j) {
     b[j] = (float)a[j];
-  }
+  });
 }
 
 // mode 0: scal[RR] = s; 1: scal[PQ] = s, scal[ALPHA] = scal[RR] / s;
@@ -252,7 +248,7 @@ hipError_t cg_init(ghost_ctx *ctx, CgWork **out, hipStream_t s) {
   for (const Run &r : pl.active_runs)
     for (int32_t o = 0; o < r.len; o += kSegLen) segs.push_back(Run{r.start + o, std::min(kSegLen, r.len - o), 0});
   w->n_segs = (int)segs.size();
-  w->n_blocks = std::max(1, (w->n_segs + kSegPerBlock - 1) / kSegPerBlock);
+  w->n_blocks = std::min(kMaxBlocks, std::max(1, (w->n_segs + kSegPerBlock - 1) / kSegPerBlock));
   const size_t n = (size_t)pl.n_lattice;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = alloc(w, &w->segs, std::max<size_t>(1, segs.size()));

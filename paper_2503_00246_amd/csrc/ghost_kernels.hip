@@ -1102,6 +1102,42 @@ hipError_t run_faces_marked(const DevPlan &p, const T *x, const T *u2, T *y, con
 
 }  // namespace
 
+// K consecutive values of one lattice line, moved in 16-byte pieces and a scalar tail.  The pieces are
+// only element-aligned, which gfx9 global loads and stores accept.
+template <typename T, int K>
+__device__ __forceinline__ void load_line(const T *__restrict__ p, bool live, T (&v)[K]) {
+  constexpr int W = 16 / (int)sizeof(T);
+  typedef T V __attribute__((ext_vector_type(W), aligned(sizeof(T))));
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < K / W; ++q) {
+      const V w = reinterpret_cast<const V *>(p)[q];
+#pragma unroll
+      for (int e = 0; e < W; ++e) v[q * W + e] = w[e];
+    }
+#pragma unroll
+    for (int i = (K / W) * W; i < K; ++i) v[i] = p[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < K; ++i) v[i] = T(0);
+  }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void store_line(T *__restrict__ p, const T (&v)[K]) {
+  constexpr int W = 16 / (int)sizeof(T);
+  typedef T V __attribute__((ext_vector_type(W), aligned(sizeof(T))));
+#pragma unroll
+  for (int q = 0; q < K / W; ++q) {
+    V w;
+#pragma unroll
+    for (int e = 0; e < W; ++e) w[e] = v[q * W + e];
+    reinterpret_cast<V *>(p)[q] = w;
+  }
+#pragma unroll
+  for (int i = (K / W) * W; i < K; ++i) p[i] = v[i];
+}
+
 // Interior-cell Laplacian (the cell term of the weak form, §2.1, on the cells the boundary does not cut,
 // evaluated by sum factorisation as in §2.5 and Algorithm 1): y += sum over inside cells K of K_K u_K with
 //   K_K = h^{d-2} sum_a (A on axis a, M on the others),
@@ -1126,9 +1162,9 @@ __global__ __launch_bounds__(kBoxThreads) void cell_kernel(const T *__restrict__
   const int64_t cell = (int64_t)blockIdx.x * CPB + c;
   const bool live = in_block && cell < n_cells;
   const int64_t line0 = live ? base[cell] + (int64_t)s1 * t1 + (int64_t)s2 * t2 : 0;
+  // the lane's x-line in 16-byte pieces (as the gather of x-normal lines), zeros for dead lanes
   T ul[K];
-#pragma unroll
-  for (int x = 0; x < K; ++x) ul[x] = live ? u[line0 + x] : T(0);
+  load_line<T, K>(u + line0, live, ul);
   // x factors within the lane
   T mx[K], ax[K];
 #pragma unroll
@@ -1198,8 +1234,11 @@ __global__ __launch_bounds__(kBoxThreads) void cell_kernel(const T *__restrict__
     wave_sync();
   }
   if (live) {
+    T yl[K];
+    load_line<T, K>(y + line0, true, yl);
 #pragma unroll
-    for (int x = 0; x < K; ++x) y[line0 + x] += scale * P[x * TL + t];
+    for (int x = 0; x < K; ++x) yl[x] += scale * P[x * TL + t];
+    store_line<T, K>(y + line0, yl);
   }
 }
 
