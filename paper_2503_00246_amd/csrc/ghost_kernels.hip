@@ -1147,16 +1147,37 @@ __device__ __forceinline__ void store_line(T *__restrict__ p, const T (&v)[K]) {
 //   3D: P = M_y (A_x u) + A_y (M_x u), Q = M_y (M_x u), result = M_z P + A_z Q;
 //   2D: result = M_y (A_x u) + A_y (M_x u).
 // The cells of one launch share no node (one parity colour), so y is read, added to and written back.
+// Where (k+1)^(d-1) lines do not divide a wavefront (3D k = 4, 5, 6), the cells are packed over the whole
+// workgroup instead (14 rather than 8 cells per workgroup at k = 5), a cell may straddle two waves, and
+// the passes meet at workgroup barriers instead of wavefront fences.
+constexpr int cell_lines(int dim, int K) { return dim == 3 ? K * K : K; }
+constexpr bool cell_dense(int dim, int K) {
+  return kBoxThreads / cell_lines(dim, K) > (kBoxThreads / 64) * (64 / cell_lines(dim, K));
+}
+constexpr int cells_per_block(int dim, int K) {
+  return cell_dense(dim, K) ? kBoxThreads / cell_lines(dim, K) : (kBoxThreads / 64) * (64 / cell_lines(dim, K));
+}
+
+template <bool kDense>
+__device__ __forceinline__ void cell_sync() {
+  if (kDense)
+    __syncthreads();
+  else
+    wave_sync();
+}
+
 template <typename T, int D, int K>
 __global__ __launch_bounds__(kBoxThreads) void cell_kernel(const T *__restrict__ u, T *__restrict__ y,
                                                            const int64_t *__restrict__ base, int64_t n_cells,
                                                            int s1, int s2, T scale) {
-  constexpr int TL = D == 3 ? K * K : K, FW = 64 / TL, CPB = (kBoxThreads / 64) * FW;
+  constexpr int TL = cell_lines(D, K), FW = 64 / TL, CPB = cells_per_block(D, K);
+  constexpr bool kDense = cell_dense(D, K);
   using Tab = gen::Tab1d<K>;
   __shared__ T sp[CPB * K * TL], sq[CPB * K * TL];  // per cell: [x][t], t = t1 + K t2
   const int tid = threadIdx.x, lane_w = tid & 63, fw = lane_w / TL;
-  const int c = (tid >> 6) * FW + fw, t = lane_w - fw * TL;
-  const bool in_block = fw < FW;
+  const int c = kDense ? tid / TL : (tid >> 6) * FW + fw;
+  const int t = kDense ? tid - c * TL : lane_w - fw * TL;
+  const bool in_block = kDense ? c < CPB : fw < FW;
   const int t1 = (D == 3) ? t % K : t;
   const int t2 = (D == 3) ? t / K : 0;
   const int64_t cell = (int64_t)blockIdx.x * CPB + c;
@@ -1186,7 +1207,7 @@ __global__ __launch_bounds__(kBoxThreads) void cell_kernel(const T *__restrict__
       Q[x * TL + t] = mx[x];
     }
   }
-  wave_sync();
+  cell_sync<kDense>();
   // y factors: the lane owns row (x = t1, z = t2) of both arrays, K values along y
   if (in_block) {
     const int row = t1 * TL + K * t2;  // element y of the row at row + y
@@ -1209,7 +1230,7 @@ __global__ __launch_bounds__(kBoxThreads) void cell_kernel(const T *__restrict__
       if (D == 3) Q[row + q] = sQ;
     }
   }
-  wave_sync();
+  cell_sync<kDense>();
   if (D == 3) {
     // z factors: the lane owns row (x = t2, y = t1), K values along z at stride K
     if (in_block) {
@@ -1231,7 +1252,7 @@ __global__ __launch_bounds__(kBoxThreads) void cell_kernel(const T *__restrict__
         P[row + q * K] = sR;
       }
     }
-    wave_sync();
+    cell_sync<kDense>();
   }
   if (live) {
     T yl[K];
@@ -1252,7 +1273,7 @@ hipError_t launch_cell_apply_t(const DevPlan &p, const T *u, T *y, hipStream_t s
     e = hipErrorInvalidValue;
 #define GHOST_CCASE(D_, K_)                                                                               \
   if (p.dim == D_ && p.k + 1 == K_) {                                                                      \
-    constexpr int64_t cpb = (kBoxThreads / 64) * (64 / (D_ == 3 ? K_ * K_ : K_));                          \
+    constexpr int64_t cpb = cells_per_block(D_, K_);                                                       \
     hipLaunchKernelGGL((cell_kernel<T, D_, K_>), dim3((unsigned)((n + cpb - 1) / cpb)), dim3(kBoxThreads),  \
                        0, s, u, y, p.inside_base + b0, n, p.stride[1], p.stride[2], scale);                \
     e = hipGetLastError();                                                                                 \
