@@ -268,9 +268,10 @@ int ghost_setup(const ghost_mesh *mesh, const ghost_levelset *ls, int k, const d
     if (rc == GHOST_OK) rc = upload(c, p.support_runs.data(), p.support_runs.size(), const_cast<ghost::Run **>(&sr));
     if (rc == GHOST_OK) rc = upload(c, p.active_runs.data(), p.active_runs.size(), const_cast<ghost::Run **>(&ar));
     if (rc == GHOST_OK) rc = upload(c, p.cls.data(), p.cls.size(), const_cast<int8_t **>(&cl));
-    const int64_t *ib = nullptr;
-    if (rc == GHOST_OK) rc = upload(c, p.inside_base.data(), p.inside_base.size(), const_cast<int64_t **>(&ib));
-    d.inside_base = ib;
+    const ghost::CellChunk *ib = nullptr;
+    if (rc == GHOST_OK)
+      rc = upload(c, p.inside_chunks.data(), p.inside_chunks.size(), const_cast<ghost::CellChunk **>(&ib));
+    d.inside_chunks = ib;
     for (int q = 0; q <= 8; ++q) d.inside_colour_begin[q] = p.inside_colour_begin[q];
     if (rc == GHOST_OK) rc = upload(c, t64.data(), t64.size(), &d.tab64);
     if (rc == GHOST_OK) rc = upload(c, t32.data(), t32.size(), &d.tab32);

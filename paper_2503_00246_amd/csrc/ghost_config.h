@@ -27,6 +27,18 @@ constexpr int kMaxBoxVisits = kBoxThreads;
 // halo slots of one box, numbered from the box's first (a box touches at most its 16^3 / 64^2 nodes)
 constexpr int kMaxBoxHalo = 1 << 13;
 
+// Interior-cell Laplacian: one x-line of a cell per lane, (k+1)^(d-1) lines per cell.  Where they do not
+// divide a wavefront (3D k = 4, 5, 6) the cells are packed over the whole workgroup (dense layout).
+// A workgroup takes a chunk of up to 2 * cells_per_block consecutive inside cells of one x-row.
+constexpr int cell_lines(int dim, int K) { return dim == 3 ? K * K : K; }
+constexpr bool cell_dense(int dim, int K) {
+  return kBoxThreads / cell_lines(dim, K) > (kBoxThreads / 64) * (64 / cell_lines(dim, K));
+}
+constexpr int cells_per_block(int dim, int K) {
+  return cell_dense(dim, K) ? kBoxThreads / cell_lines(dim, K) : (kBoxThreads / 64) * (64 / cell_lines(dim, K));
+}
+constexpr int cell_chunk(int dim, int K) { return 2 * cells_per_block(dim, K); }
+
 // Threads per face: one per tangential node line, (k+1)^(d-1).
 constexpr int lines_per_face(int dim, int k) { return dim == 3 ? (k + 1) * (k + 1) : (k + 1); }
 

@@ -77,7 +77,7 @@ struct DevPlan {
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 
   // inside cells of the interior Laplacian (first-node lattice index), by parity colour
-  const int64_t *inside_base = nullptr;
+  const CellChunk *inside_chunks = nullptr;
   int64_t inside_colour_begin[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
   double *tab64 = nullptr;

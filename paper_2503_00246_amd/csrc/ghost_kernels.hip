@@ -1146,17 +1146,14 @@ __device__ __forceinline__ void store_line(T *__restrict__ p, const T (&v)[K]) {
 // act within the lane, the y and z factors by rows in the wave's LDS, as in the face's mass passes:
 //   3D: P = M_y (A_x u) + A_y (M_x u), Q = M_y (M_x u), result = M_z P + A_z Q;
 //   2D: result = M_y (A_x u) + A_y (M_x u).
-// The cells of one launch share no node (one parity colour), so y is read, added to and written back.
+// A workgroup takes a chunk of consecutive inside cells of one x-row: the cells at even positions of the
+// chunk first, then, after a workgroup barrier, those at odd positions, so that no two cells applied at
+// once share a node and the rows' cache lines are reused between the two phases.  Neighbouring chunks
+// of a row (one shared node) and neighbouring rows are in different launches (colours), so y is read,
+// added to and written back without atomics.
 // Where (k+1)^(d-1) lines do not divide a wavefront (3D k = 4, 5, 6), the cells are packed over the whole
-// workgroup instead (14 rather than 8 cells per workgroup at k = 5), a cell may straddle two waves, and
+// workgroup instead (14 rather than 8 cells per phase at k = 5), a cell may straddle two waves, and
 // the passes meet at workgroup barriers instead of wavefront fences.
-constexpr int cell_lines(int dim, int K) { return dim == 3 ? K * K : K; }
-constexpr bool cell_dense(int dim, int K) {
-  return kBoxThreads / cell_lines(dim, K) > (kBoxThreads / 64) * (64 / cell_lines(dim, K));
-}
-constexpr int cells_per_block(int dim, int K) {
-  return cell_dense(dim, K) ? kBoxThreads / cell_lines(dim, K) : (kBoxThreads / 64) * (64 / cell_lines(dim, K));
-}
 
 template <bool kDense>
 __device__ __forceinline__ void cell_sync() {
@@ -1168,8 +1165,8 @@ __device__ __forceinline__ void cell_sync() {
 
 template <typename T, int D, int K>
 __global__ __launch_bounds__(kBoxThreads) void cell_kernel(const T *__restrict__ u, T *__restrict__ y,
-                                                           const int64_t *__restrict__ base, int64_t n_cells,
-                                                           int s1, int s2, T scale) {
+                                                           const CellChunk *__restrict__ chunks, int s1, int s2,
+                                                           T scale) {
   constexpr int TL = cell_lines(D, K), FW = 64 / TL, CPB = cells_per_block(D, K);
   constexpr bool kDense = cell_dense(D, K);
   using Tab = gen::Tab1d<K>;
@@ -1180,86 +1177,91 @@ __global__ __launch_bounds__(kBoxThreads) void cell_kernel(const T *__restrict__
   const bool in_block = kDense ? c < CPB : fw < FW;
   const int t1 = (D == 3) ? t % K : t;
   const int t2 = (D == 3) ? t / K : 0;
-  const int64_t cell = (int64_t)blockIdx.x * CPB + c;
-  const bool live = in_block && cell < n_cells;
-  const int64_t line0 = live ? base[cell] + (int64_t)s1 * t1 + (int64_t)s2 * t2 : 0;
-  // the lane's x-line in 16-byte pieces (as the gather of x-normal lines), zeros for dead lanes
-  T ul[K];
-  load_line<T, K>(u + line0, live, ul);
-  // x factors within the lane
-  T mx[K], ax[K];
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    T m = T(0), a = T(0);
-#pragma unroll
-    for (int x = 0; x < K; ++x) {
-      m = fma(T(Tab::M[q * K + x]), ul[x], m);
-      a = fma(T(Tab::A[q * K + x]), ul[x], a);
-    }
-    mx[q] = m;
-    ax[q] = a;
-  }
+  const CellChunk ch = chunks[blockIdx.x];
   T *P = &sp[c * K * TL], *Q = &sq[c * K * TL];
-  if (in_block) {
-#pragma unroll
-    for (int x = 0; x < K; ++x) {
-      P[x * TL + t] = ax[x];
-      Q[x * TL + t] = mx[x];
-    }
-  }
-  cell_sync<kDense>();
-  // y factors: the lane owns row (x = t1, z = t2) of both arrays, K values along y
-  if (in_block) {
-    const int row = t1 * TL + K * t2;  // element y of the row at row + y
-    T pa[K], qm[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) {
-      pa[m] = P[row + m];
-      qm[m] = Q[row + m];
-    }
+  for (int phase = 0; phase < 2; ++phase) {
+    const int pos = 2 * c + phase;  // the lane's cell in the chunk
+    const bool live = in_block && pos < ch.count;
+    const int64_t line0 = live ? ch.base + (int64_t)(K - 1) * pos + (int64_t)s1 * t1 + (int64_t)s2 * t2 : 0;
+    // the lane's x-line in 16-byte pieces (as the gather of x-normal lines), zeros for dead lanes
+    T ul[K];
+    load_line<T, K>(u + line0, live, ul);
+    // x factors within the lane
+    T mx[K], ax[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-      T sP = T(0), sQ = T(0);
+      T m = T(0), a = T(0);
 #pragma unroll
-      for (int m = 0; m < K; ++m) {
-        sP = fma(T(Tab::M[q * K + m]), pa[m], sP);
-        sP = fma(T(Tab::A[q * K + m]), qm[m], sP);
-        sQ = fma(T(Tab::M[q * K + m]), qm[m], sQ);
+      for (int x = 0; x < K; ++x) {
+        m = fma(T(Tab::M[q * K + x]), ul[x], m);
+        a = fma(T(Tab::A[q * K + x]), ul[x], a);
       }
-      P[row + q] = sP;
-      if (D == 3) Q[row + q] = sQ;
+      mx[q] = m;
+      ax[q] = a;
     }
-  }
-  cell_sync<kDense>();
-  if (D == 3) {
-    // z factors: the lane owns row (x = t2, y = t1), K values along z at stride K
     if (in_block) {
-      const int row = t2 * TL + t1;
-      T pa[K], qm[K];
 #pragma unroll
-      for (int m = 0; m < K; ++m) {
-        pa[m] = P[row + m * K];
-        qm[m] = Q[row + m * K];
-      }
-#pragma unroll
-      for (int q = 0; q < K; ++q) {
-        T sR = T(0);
-#pragma unroll
-        for (int m = 0; m < K; ++m) {
-          sR = fma(T(Tab::M[q * K + m]), pa[m], sR);
-          sR = fma(T(Tab::A[q * K + m]), qm[m], sR);
-        }
-        P[row + q * K] = sR;
+      for (int x = 0; x < K; ++x) {
+        P[x * TL + t] = ax[x];
+        Q[x * TL + t] = mx[x];
       }
     }
     cell_sync<kDense>();
-  }
-  if (live) {
-    T yl[K];
-    load_line<T, K>(y + line0, true, yl);
+    // y factors: the lane owns row (x = t1, z = t2) of both arrays, K values along y
+    if (in_block) {
+      const int row = t1 * TL + K * t2;  // element y of the row at row + y
+      T pa[K], qm[K];
 #pragma unroll
-    for (int x = 0; x < K; ++x) yl[x] += scale * P[x * TL + t];
-    store_line<T, K>(y + line0, yl);
+      for (int m = 0; m < K; ++m) {
+        pa[m] = P[row + m];
+        qm[m] = Q[row + m];
+      }
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        T sP = T(0), sQ = T(0);
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+          sP = fma(T(Tab::M[q * K + m]), pa[m], sP);
+          sP = fma(T(Tab::A[q * K + m]), qm[m], sP);
+          sQ = fma(T(Tab::M[q * K + m]), qm[m], sQ);
+        }
+        P[row + q] = sP;
+        if (D == 3) Q[row + q] = sQ;
+      }
+    }
+    cell_sync<kDense>();
+    if (D == 3) {
+      // z factors: the lane owns row (x = t2, y = t1), K values along z at stride K
+      if (in_block) {
+        const int row = t2 * TL + t1;
+        T pa[K], qm[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+          pa[m] = P[row + m * K];
+          qm[m] = Q[row + m * K];
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          T sR = T(0);
+#pragma unroll
+          for (int m = 0; m < K; ++m) {
+            sR = fma(T(Tab::M[q * K + m]), pa[m], sR);
+            sR = fma(T(Tab::A[q * K + m]), qm[m], sR);
+          }
+          P[row + q * K] = sR;
+        }
+      }
+      cell_sync<kDense>();
+    }
+    if (live) {
+      T yl[K];
+      load_line<T, K>(y + line0, true, yl);
+#pragma unroll
+      for (int x = 0; x < K; ++x) yl[x] += scale * P[x * TL + t];
+      store_line<T, K>(y + line0, yl);
+    }
+    // the even cells' updates of y (and their reads of P, Q) complete before the odd cells start
+    __syncthreads();
   }
 }
 
@@ -1268,14 +1270,13 @@ hipError_t launch_cell_apply_t(const DevPlan &p, const T *u, T *y, hipStream_t s
   const T scale = (T)(p.dim == 3 ? p.h : 1.0);  // h^{d-2}
   hipError_t e = hipSuccess;
   for (int col = 0; col < (1 << p.dim) && e == hipSuccess; ++col) {
-    const int64_t b0 = p.inside_colour_begin[col], n = p.inside_colour_begin[col + 1] - b0;
+    const int64_t b0 = p.inside_colour_begin[col], n = p.inside_colour_begin[col + 1] - b0;  // chunks
     if (n == 0) continue;
     e = hipErrorInvalidValue;
 #define GHOST_CCASE(D_, K_)                                                                               \
   if (p.dim == D_ && p.k + 1 == K_) {                                                                      \
-    constexpr int64_t cpb = cells_per_block(D_, K_);                                                       \
-    hipLaunchKernelGGL((cell_kernel<T, D_, K_>), dim3((unsigned)((n + cpb - 1) / cpb)), dim3(kBoxThreads),  \
-                       0, s, u, y, p.inside_base + b0, n, p.stride[1], p.stride[2], scale);                \
+    hipLaunchKernelGGL((cell_kernel<T, D_, K_>), dim3((unsigned)n), dim3(kBoxThreads), 0, s, u, y,        \
+                       p.inside_chunks + b0, p.stride[1], p.stride[2], scale);                              \
     e = hipGetLastError();                                                                                 \
   }
     GHOST_CCASE(2, 2) GHOST_CCASE(2, 3) GHOST_CCASE(2, 4) GHOST_CCASE(2, 5) GHOST_CCASE(2, 6) GHOST_CCASE(2, 7)

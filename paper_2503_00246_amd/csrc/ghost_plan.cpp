@@ -472,23 +472,35 @@ std::string build_plan(Plan &p, int dim, const int n[3], const double lo[3], dou
       }
     merge_runs(iv, p.L[0], p.active_runs, p.n_active);
   }
-  // ---- inside cells by parity colour
+  // ---- inside cells in chunks along x, by colour
   {
-    std::vector<std::vector<int64_t>> byc(1 << dim);
+    const int chunk = cell_chunk(dim, k + 1);
+    std::vector<std::vector<CellChunk>> byc(1 << dim);
     for (int c2 = 0; c2 < p.n[2]; ++c2)
       for (int c1 = 0; c1 < p.n[1]; ++c1)
-        for (int c0 = 0; c0 < p.n[0]; ++c0)
-          if (cls_at(c0, c1, c2) == GHOST_INSIDE) {
-            const int col = (c0 & 1) + (dim >= 2 ? 2 * (c1 & 1) : 0) + (dim >= 3 ? 4 * (c2 & 1) : 0);
-            byc[col].push_back((int64_t)k * c0 + p.stride[1] * ((int64_t)k * c1) + p.stride[2] * ((int64_t)k * c2));
+        for (int c0 = 0; c0 < p.n[0];) {
+          if (cls_at(c0, c1, c2) != GHOST_INSIDE) {
+            ++c0;
+            continue;
           }
-    p.inside_base.clear();
+          int e0 = c0;
+          while (e0 < p.n[0] && cls_at(e0, c1, c2) == GHOST_INSIDE) ++e0;
+          // the run [c0, e0), cut into chunks; neighbouring chunks of a run share one node and get
+          // different colours, runs of one row are at least a cell apart
+          for (int j = 0, a = c0; a < e0; ++j, a += chunk) {
+            const int col = (j & 1) + (dim >= 2 ? 2 * (c1 & 1) : 0) + (dim >= 3 ? 4 * (c2 & 1) : 0);
+            const int64_t base = (int64_t)k * a + p.stride[1] * ((int64_t)k * c1) + p.stride[2] * ((int64_t)k * c2);
+            byc[col].push_back({base, std::min(chunk, e0 - a), 0});
+          }
+          c0 = e0;
+        }
+    p.inside_chunks.clear();
     for (int col = 0; col <= 8; ++col) p.inside_colour_begin[col] = 0;
     for (int col = 0; col < (1 << dim); ++col) {
-      p.inside_colour_begin[col] = (int64_t)p.inside_base.size();
-      p.inside_base.insert(p.inside_base.end(), byc[col].begin(), byc[col].end());
+      p.inside_colour_begin[col] = (int64_t)p.inside_chunks.size();
+      p.inside_chunks.insert(p.inside_chunks.end(), byc[col].begin(), byc[col].end());
     }
-    for (int col = 1 << dim; col <= 8; ++col) p.inside_colour_begin[col] = (int64_t)p.inside_base.size();
+    for (int col = 1 << dim; col <= 8; ++col) p.inside_colour_begin[col] = (int64_t)p.inside_chunks.size();
     // their distinct nodes, counted through x-runs as for the active nodes
     std::vector<Interval> iv;
     for (int c2 = 0; c2 < p.n[2]; ++c2)

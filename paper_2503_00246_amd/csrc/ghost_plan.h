@@ -52,6 +52,13 @@ struct BoxLine {
 // that counts it in reductions) is the one with half 0 or 1.
 using Visit = uint64_t;
 
+// A chunk of the interior Laplacian: `count` consecutive inside cells of one x-row, the first with
+// lattice index `base` of its first node.
+struct CellChunk {
+  int64_t base;
+  int32_t count, pad;
+};
+
 struct BoxRun {          // a run of touched box nodes along x
   int64_t start;         // lattice index of the first node
   int32_t acc;           // box-linear index x + E*(y + E*z) of the first node (E = box_extent)
@@ -103,9 +110,10 @@ struct Plan {
   std::vector<Run> active_runs;        // nodes of active cells
   int64_t n_active = 0;
 
-  // inside cells (the interior Laplacian): lattice index of each cell's first node, grouped by colour
-  // (c0 mod 2) + 2 (c1 mod 2) + 4 (c2 mod 2), so that no two cells of a colour share a node
-  std::vector<int64_t> inside_base;
+  // inside cells (the interior Laplacian): each run of consecutive inside cells along x cut into chunks
+  // of at most cell_chunk(dim, k+1) cells, grouped by colour (chunk index in the run mod 2) +
+  // 2 (c1 mod 2) + 4 (c2 mod 2), so that no two chunks of a colour share a node
+  std::vector<CellChunk> inside_chunks;
   int64_t n_inside = 0;  // distinct nodes of the inside cells
   int64_t inside_colour_begin[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
