@@ -121,7 +121,8 @@ typedef struct {
   int64_t n_halo_slots;       /* box scatter: halo slots (values passed between the two kernels) */
   int64_t n_halo_nodes;       /* box scatter: support nodes on shared box faces */
   int brick;                  /* box scatter: brick edge in cells */
-  double flops_per_face;      /* arithmetic of one face in the kernel, 2 per FMA */
+  double flops_per_face;      /* arithmetic of one face in the kernel, 2 per FMA (with the order
+                                 coupling for GHOST_MACRO_PATCH) */
   double bytes_fp64;          /* compulsory bytes of an accumulating FP64 apply: 24 per support DoF */
   double bytes_fp32;          /* same for FP32: 12 per support DoF */
   int64_t n_inside_dofs;      /* nodes of inside cells (the interior Laplacian's nodes) */

@@ -530,7 +530,11 @@ int ghost_info(const ghost_ctx *ctx, ghost_stats *out) {
   out->brick = p.brick;
   out->n_halo_slots = p.n_slots;
   out->n_halo_nodes = (int64_t)p.halo_node.size();
-  out->flops_per_face = 2.0 * (2.0 * p.k * (2 * p.k + 1) * tang + (double)(p.dim - 1) * p.k * tang * K);
+  // contraction and expansion 2k(2k+1) per tangential line, masses (d-1)k(k+1) per line; the macro-patch
+  // form also couples the orders, ceil(k^2 / 2) nonzeros of H per line
+  const double coupling = ctx->dev.macro ? (double)((p.k * p.k + 1) / 2) * tang : 0.0;
+  out->flops_per_face =
+      2.0 * (2.0 * p.k * (2 * p.k + 1) * tang + (double)(p.dim - 1) * p.k * tang * K + coupling);
   out->bytes_fp64 = 24.0 * (double)p.n_support;
   out->bytes_fp32 = 12.0 * (double)p.n_support;
   return GHOST_OK;

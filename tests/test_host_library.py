@@ -136,6 +136,10 @@ def test_flop_count_formula():
         k, d = w.k, w.d
         fma = 2 * k * (2 * k + 1) * (k + 1) ** (d - 1) + (d - 1) * k * (k + 1) ** d
         assert _host(w).stats["flops_per_face"] == 2 * fma
+        # the macro-patch form adds the order coupling: entries (i, j) with i + j even, per line
+        pairs = sum(1 for i in range(k) for j in range(k) if (i + j) % 2 == 0)
+        macro = GhostOperator.from_workload(w, device=-1, penalty="macro")
+        assert macro.stats["flops_per_face"] == 2 * (fma + pairs * (k + 1) ** (d - 1))
 
 
 @pytest.mark.parametrize("name", ["disk2d_q2_32", "ball3d_q3_64"])
