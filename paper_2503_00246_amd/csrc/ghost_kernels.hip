@@ -10,6 +10,9 @@
 //     y_F = sum_j gs_j (x) b_j           (2k+1) x (k+1)^{d-1}
 // which costs 2k(2k+1)(k+1)^{d-1} + 2(d-1)k(k+1)^d flops instead of the dense
 // (2k+1)^2 (k+1)^{2(d-1)} of the patch matrix.
+// The macro-patch stabilisation (§2.2, its alternative form) runs the same steps with the orders coupled
+// before the expansion, y_F = gamma_M h^{d-2} sum_i g_i (x) (sum_j H_ij b_j), H a fixed k x k matrix
+// (box kernel only).
 //
 // Work mapping: one thread per tangential node line of a face ((k+1)^{d-1} threads per
 // face), several faces of one normal axis per 256-thread workgroup.  A thread gathers its
@@ -844,9 +847,10 @@ __device__ __forceinline__ void box_body(
 #define GHOST_BOX_ARGS x, u2, y, halo, partial, boxes, visits, lines, tab, s1, s2, accumulate, n_boxes, sched
 
 // Two blocks of 512 threads per CU need at most 128 VGPRs (4 waves per SIMD); the compiler is held to
-// that for the apply (FP32 at every degree and FP64 up to k = 6 fit without spilling).  The VJP and the
-// FP64 apply at k = 7 carry more live values and run one block per CU instead: spilled values reloaded
-// behind a gather would make the flush wait for it.
+// that for the apply (FP32 at every degree and FP64 up to k = 4 fit without spilling; FP64 at k = 5 and
+// 6 spills a few values, reloaded once per box; at k = 6 one of them is also stored once per face round).
+// The VJP and the FP64 apply at k = 7 carry more live values and run one block per CU instead: spilled
+// values reloaded behind a gather would make the flush wait for it.
 template <typename T, int D, int K, bool VJP, bool MACRO>
 __global__ __launch_bounds__(kBoxThreads) __attribute__((amdgpu_waves_per_eu(4))) void box_kernel(
     GHOST_BOX_PARAMS) {
