@@ -206,8 +206,8 @@ int ghost_diag(ghost_ctx *ctx, double *diag, int accumulate, void *stream);
  *   y += sum over INSIDE cells K of K_K u_K,  [K_K]_ab = integral_K grad phi_a . grad phi_b,
  * so that ghost_cell_apply followed by ghost_apply (accumulate = 1) gives (K_inside + G) u, the
  * operator of the paper's vmult without its cut-cell part.  u, y: DEVICE arrays of n_lattice values
- * (u != y); y is only added to (pass a zeroed y for K_inside u).  Stream-ordered; one launch per parity
- * colour of the cells (cells of a colour share no node), no atomics.
+ * (u != y); y is only added to (pass a zeroed y for K_inside u).  Stream-ordered; one launch per colour
+ * of the chunks of consecutive inside cells along x (chunks of a colour share no node), no atomics.
  */
 int ghost_cell_apply(ghost_ctx *ctx, const double *u, double *y, void *stream);
 int ghost_cell_apply_f32(ghost_ctx *ctx, const float *u, float *y, void *stream);
