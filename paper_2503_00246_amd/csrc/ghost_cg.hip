@@ -88,19 +88,46 @@ __global__ void start_kernel(const Run *segs, int n_segs, const double *src, T *
   block_partial(acc, partial);
 }
 
-// optionally p = z + beta p, then q = mdiag * p
+// Optionally x += alpha p (the previous step's update of x, deferred to this pass, which reads p anyway),
+// optionally p = z + beta p, then q = mdiag * p; partial <p, q>, the mass part of <p, A p>.
 template <typename T>
-__global__ void pq_kernel(const Run *segs, int n_segs, T *p, const T *r, T *q, const T *mdiag, const T *dinv,
-                          const double *scal, int update_p) {
-  const T beta = (T)scal[S_BETA];
+__global__ void pq_kernel(const Run *segs, int n_segs, T *x, T *p, const T *r, T *q, const T *mdiag, const T *dinv,
+                          const double *scal, int update_p, int update_x, double *partial) {
+  const T beta = (T)scal[S_BETA], alpha = (T)scal[S_ALPHA];
+  double acc = 0.0;
   for_active(segs, n_segs, [&](int64_t j) {
     T pv = p[j];
+    if (update_x) x[j] += alpha * pv;
     if (update_p) {
       pv = precond(dinv, j, r[j]) + beta * pv;
       p[j] = pv;
     }
-    q[j] = mdiag[j] * pv;
+    const T qv = mdiag[j] * pv;
+    q[j] = qv;
+    acc += (double)pv * (double)qv;
   });
+  block_partial(acc, partial);
+}
+
+// partial <p, q - mdiag p> over the support nodes: the ghost part of <p, A p> (G p vanishes elsewhere),
+// with mdiag p rounded as pq_kernel rounded it into q.
+template <typename T>
+__global__ void ghost_dot_kernel(const Run *segs, int n_segs, const T *p, const T *q, const T *mdiag,
+                                 double *partial) {
+  double acc = 0.0;
+  for_active(segs, n_segs, [&](int64_t j) {
+    const T pv = p[j];
+    const T mp = mdiag[j] * pv;
+    acc += (double)pv * ((double)q[j] - (double)mp);
+  });
+  block_partial(acc, partial);
+}
+
+// x += alpha p (the deferred update, when the solve needs x)
+template <typename T>
+__global__ void axpy_kernel(const Run *segs, int n_segs, T *x, const T *p, const double *scal) {
+  const T alpha = (T)scal[S_ALPHA];
+  for_active(segs, n_segs, [&](int64_t j) { x[j] += alpha * p[j]; });
 }
 
 template <typename T>
@@ -112,14 +139,13 @@ __global__ void dot_kernel(const Run *segs, int n_segs, const T *a, const T *b, 
   block_partial(acc, partial);
 }
 
-// x += alpha p, r -= alpha q; partial <r, z>
+// r -= alpha q; partial <r, z> (x += alpha p is deferred to the next pq_kernel or axpy_kernel)
 template <typename T>
-__global__ void xr_kernel(const Run *segs, int n_segs, T *x, T *r, const T *p, const T *q, const T *dinv,
-                          const double *scal, double *partial) {
+__global__ void xr_kernel(const Run *segs, int n_segs, T *r, const T *q, const T *dinv, const double *scal,
+                          double *partial) {
   const T alpha = (T)scal[S_ALPHA];
   double acc = 0.0;
   for_active(segs, n_segs, [&](int64_t j) {
-    x[j] += alpha * p[j];
     const T rv = r[j] - alpha * q[j];
     r[j] = rv;
     acc += (double)rv * (double)precond(dinv, j, rv);
@@ -179,11 +205,13 @@ __global__ void cast_kernel(const Run *segs, int n_segs, const double *a, float 
 
 // mode 0: scal[RR] = s; 1: scal[PQ] = s, scal[ALPHA] = scal[RR] / s;
 // 2: scal[BETA] = s / scal[RR], scal[RR] = s; 3: scal[TMP] = s
-__global__ void reduce_kernel(const double *partial, int n, double *scal, int mode) {
+// (the partial sums of two arrays: n of `partial` and n2 of `partial2`)
+__global__ void reduce_kernel(const double *partial, int n, const double *partial2, int n2, double *scal, int mode) {
   __shared__ double red[kBlockThreads];
   const int tid = threadIdx.x;
   double s = 0.0;
   for (int i = tid; i < n; i += kBlockThreads) s += partial[i];
+  for (int i = tid; i < n2; i += kBlockThreads) s += partial2[i];
   red[tid] = s;
   __syncthreads();
   for (int w = kBlockThreads / 2; w > 0; w >>= 1) {
@@ -213,6 +241,9 @@ __global__ void reduce_kernel(const double *partial, int n, double *scal, int mo
 struct CgWork {
   Run *segs = nullptr;
   int n_segs = 0, n_blocks = 0;
+  Run *ssegs = nullptr;  // support nodes (G p vanishes elsewhere), cut like the active ones
+  int n_ssegs = 0, n_sblocks = 0;
+  double *partial2 = nullptr;
   double *mdiag = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *scal = nullptr, *partial = nullptr;
   float *mdiag32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *e32 = nullptr;
   double *dinv = nullptr;  // Jacobi preconditioner 1 / diag(M + G), rebuilt per preconditioned solve
@@ -249,11 +280,20 @@ hipError_t cg_init(ghost_ctx *ctx, CgWork **out, hipStream_t s) {
     for (int32_t o = 0; o < r.len; o += kSegLen) segs.push_back(Run{r.start + o, std::min(kSegLen, r.len - o), 0});
   w->n_segs = (int)segs.size();
   w->n_blocks = std::min(kMaxBlocks, std::max(1, (w->n_segs + kSegPerBlock - 1) / kSegPerBlock));
+  std::vector<Run> ssegs;
+  for (const Run &r : pl.support_runs)
+    for (int32_t o = 0; o < r.len; o += kSegLen) ssegs.push_back(Run{r.start + o, std::min(kSegLen, r.len - o), 0});
+  w->n_ssegs = (int)ssegs.size();
+  w->n_sblocks = std::min(kMaxBlocks, std::max(1, (w->n_ssegs + kSegPerBlock - 1) / kSegPerBlock));
   const size_t n = (size_t)pl.n_lattice;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = alloc(w, &w->segs, std::max<size_t>(1, segs.size()));
   if (e == hipSuccess && !segs.empty())
     e = hipMemcpy(w->segs, segs.data(), segs.size() * sizeof(Run), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = alloc(w, &w->ssegs, std::max<size_t>(1, ssegs.size()));
+  if (e == hipSuccess && !ssegs.empty())
+    e = hipMemcpy(w->ssegs, ssegs.data(), ssegs.size() * sizeof(Run), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = alloc(w, &w->partial2, (size_t)w->n_sblocks);
   if (e == hipSuccess) e = alloc(w, &w->mdiag, n);
   if (e == hipSuccess) e = alloc(w, &w->r, n);
   if (e == hipSuccess) e = alloc(w, &w->p, n);
@@ -291,9 +331,25 @@ struct Runner {
   hipError_t err = hipSuccess;
   dim3 grid, block{kBlockThreads};
   Runner(const DevPlan &d, CgWork *w_, hipStream_t s_) : dp(d), w(w_), s(s_), grid(w_->n_blocks) {}
-  void reduce(int mode) {
+  void reduce(int mode, bool with_ghost_dot = false) {
     if (err != hipSuccess) return;
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlockThreads), 0, s, w->partial, w->n_blocks, w->scal, mode);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlockThreads), 0, s, w->partial, w->n_blocks,
+                       (const double *)w->partial2, with_ghost_dot ? w->n_sblocks : 0, w->scal, mode);
+    err = hipGetLastError();
+  }
+  // <p, A p> into the reduction of mode 1 (alpha): the mass part from pq_kernel, the ghost part here
+  template <typename T>
+  void ghost_dot(const T *p, const T *q, const T *mdiag) {
+    if (err != hipSuccess) return;
+    hipLaunchKernelGGL(ghost_dot_kernel<T>, dim3(w->n_sblocks), block, 0, s, w->ssegs, w->n_ssegs, p, q, mdiag,
+                       w->partial2);
+    err = hipGetLastError();
+    reduce(1, true);
+  }
+  template <typename T>
+  void flush_x(T *x, const T *p) {
+    if (err != hipSuccess) return;
+    hipLaunchKernelGGL(axpy_kernel<T>, grid, block, 0, s, w->segs, w->n_segs, x, p, (const double *)w->scal);
     err = hipGetLastError();
   }
   void check() {
@@ -370,19 +426,19 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
     double rr = R.read(S_RR);  // <r, z>
     double rr_true = jac ? bnorm * bnorm : rr;
     const int every = opts.check_every > 0 ? opts.check_every : 50;
-    bool update_p = false;
+    bool update_p = false, x_pending = false;  // x_pending: x still lacks alpha p of the last step
     while (R.err == hipSuccess && std::sqrt(rr_true) > target && it < opts.max_iter) {
-      hipLaunchKernelGGL(pq_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, w->p, (const double *)w->r,
-                         w->q, (const double *)w->mdiag, dinv, (const double *)w->scal, (int)update_p);
+      hipLaunchKernelGGL(pq_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, x, w->p, (const double *)w->r,
+                         w->q, (const double *)w->mdiag, dinv, (const double *)w->scal, (int)update_p,
+                         (int)x_pending, w->partial);
       R.check();
+      x_pending = false;
       if (R.err == hipSuccess) R.err = launch_apply_f64(dp, w->p, w->q, true, s);
-      hipLaunchKernelGGL(dot_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, (const double *)w->p,
-                         (const double *)w->q, w->partial);
+      R.ghost_dot<double>(w->p, w->q, w->mdiag);
+      hipLaunchKernelGGL(xr_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, w->r, (const double *)w->q, dinv,
+                         (const double *)w->scal, w->partial);
       R.check();
-      R.reduce(1);
-      hipLaunchKernelGGL(xr_kernel<double>, grid, block, 0, s, w->segs, w->n_segs, x, w->r, (const double *)w->p,
-                         (const double *)w->q, dinv, (const double *)w->scal, w->partial);
-      R.check();
+      x_pending = true;
       R.reduce(2);
       update_p = true;
       ++it;
@@ -393,9 +449,12 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
       }
       if ((poll && std::sqrt(rr) <= target) || it % every == 0) {
         // replace the recursive residual by the true one (the search direction is kept)
+        R.flush_x(x, (const double *)w->p);
+        x_pending = false;
         rr_true = R.true_residual(b, x, w->r, dinv);
       }
     }
+    if (x_pending) R.flush_x(x, (const double *)w->p);
     res.outer = 1;
   } else {
     hipLaunchKernelGGL(add_kernel, grid, block, 0, s, w->segs, w->n_segs, x, (const float *)nullptr, 1);
@@ -410,19 +469,19 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
       R.reduce(0);
       double rr = R.read(S_RR);
       const double inner_target = opts.inner_tol * std::sqrt(rr);
-      bool update_p = false;
+      bool update_p = false, e_pending = false;  // e_pending: e still lacks alpha p of the last step
       while (R.err == hipSuccess && std::sqrt(rr) > inner_target && it < opts.max_iter) {
-        hipLaunchKernelGGL(pq_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, w->p32, (const float *)w->r32,
-                           w->q32, (const float *)w->mdiag32, dinv32, (const double *)w->scal, (int)update_p);
+        hipLaunchKernelGGL(pq_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, w->e32, w->p32,
+                           (const float *)w->r32, w->q32, (const float *)w->mdiag32, dinv32, (const double *)w->scal,
+                           (int)update_p, (int)e_pending, w->partial);
         R.check();
+        e_pending = false;
         if (R.err == hipSuccess) R.err = launch_apply_f32(dp, w->p32, w->q32, true, s);
-        hipLaunchKernelGGL(dot_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, (const float *)w->p32,
-                           (const float *)w->q32, w->partial);
+        R.ghost_dot<float>(w->p32, w->q32, w->mdiag32);
+        hipLaunchKernelGGL(xr_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, w->r32, (const float *)w->q32,
+                           dinv32, (const double *)w->scal, w->partial);
         R.check();
-        R.reduce(1);
-        hipLaunchKernelGGL(xr_kernel<float>, grid, block, 0, s, w->segs, w->n_segs, w->e32, w->r32,
-                           (const float *)w->p32, (const float *)w->q32, dinv32, (const double *)w->scal, w->partial);
-        R.check();
+        e_pending = true;
         R.reduce(2);
         update_p = true;
         ++it;
@@ -431,6 +490,7 @@ int cg_solve(ghost_ctx *ctx, const double *b, double *x, const ghost_cg_opts &op
           if (!std::isfinite(rr)) break;
         }
       }
+      if (e_pending) R.flush_x(w->e32, (const float *)w->p32);
       hipLaunchKernelGGL(add_kernel, grid, block, 0, s, w->segs, w->n_segs, x, (const float *)w->e32, 0);
       R.check();
       ++res.outer;
