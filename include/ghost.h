@@ -128,6 +128,7 @@ typedef struct {
   int64_t n_inside_dofs;      /* nodes of inside cells (the interior Laplacian's nodes) */
   int n_gamma;                /* coefficients of the penalty: k, or 1 with GHOST_MACRO_PATCH */
   int macro;                  /* 1 for a GHOST_MACRO_PATCH context */
+  int64_t n_cell_chunks;      /* chunks of the interior Laplacian (see ghost_cell_chunks) */
 } ghost_stats;
 
 /*
@@ -290,6 +291,14 @@ int ghost_tables(const ghost_ctx *ctx, double *jumps, double *mass, double *node
  *           (-1 = written to y)                                           (capacity run_cap runs)
  * GHOST_EINVAL if a capacity is too small.
  */
+/*
+ * Copy the chunks of the interior Laplacian (ghost_cell_apply) to the HOST array `out` (inspection and
+ * tests), 3 int64 per chunk: lattice index of the first node of its first cell, the number of
+ * consecutive inside cells along x it holds, and its colour (the launch it runs in; chunks of one
+ * colour share no node).  `cap` is the capacity in chunks; GHOST_EINVAL if it is below n_cell_chunks.
+ */
+int ghost_cell_chunks(const ghost_ctx *ctx, int64_t *out, int64_t cap);
+
 int ghost_box_layout(const ghost_ctx *ctx, int32_t *boxes, int64_t box_cap, uint64_t *visits,
                      int64_t visit_cap, int64_t *runs, int64_t run_cap);
 

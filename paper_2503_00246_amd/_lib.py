@@ -19,7 +19,8 @@ GHOST_CG_NONE, GHOST_CG_JACOBI = 0, 1
 EXPORTS = ["ghost_setup", "ghost_set_gamma", "ghost_apply", "ghost_apply_f32", "ghost_vjp",
            "ghost_mass_diag", "ghost_cg", "ghost_info", "ghost_faces", "ghost_tables", "ghost_box_layout",
            "ghost_destroy", "ghost_last_error", "ghost_set_timing", "ghost_kernel_times", "ghost_diag",
-           "ghost_face_bench", "ghost_face_bench_f32", "ghost_cell_apply", "ghost_cell_apply_f32"]
+           "ghost_face_bench", "ghost_face_bench_f32", "ghost_cell_apply", "ghost_cell_apply_f32",
+           "ghost_cell_chunks"]
 
 
 class GhostMesh(ctypes.Structure):
@@ -44,7 +45,7 @@ class GhostStats(ctypes.Structure):
                 ("n_halo_nodes", ctypes.c_int64), ("brick", ctypes.c_int),
                 ("flops_per_face", ctypes.c_double), ("bytes_fp64", ctypes.c_double),
                 ("bytes_fp32", ctypes.c_double), ("n_inside_dofs", ctypes.c_int64),
-                ("n_gamma", ctypes.c_int), ("macro", ctypes.c_int)]
+                ("n_gamma", ctypes.c_int), ("macro", ctypes.c_int), ("n_cell_chunks", ctypes.c_int64)]
 
     def as_dict(self):
         out = {}
@@ -94,6 +95,7 @@ def load(path=LIB_PATH):
     lib.ghost_face_bench.argtypes = [P, P, P, c_i64, c_int, P]
     lib.ghost_cell_apply.argtypes = [P, P, P, P]
     lib.ghost_cell_apply_f32.argtypes = [P, P, P, P]
+    lib.ghost_cell_chunks.argtypes = [P, ctypes.POINTER(ctypes.c_int64), c_i64]
     lib.ghost_face_bench_f32.argtypes = [P, P, P, c_i64, c_int, P]
     lib.ghost_cg.argtypes = [P, P, P, ctypes.POINTER(GhostCgOpts), ctypes.POINTER(GhostCgResult), P]
     lib.ghost_info.argtypes = [P, ctypes.POINTER(GhostStats)]

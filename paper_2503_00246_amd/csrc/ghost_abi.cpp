@@ -519,6 +519,7 @@ int ghost_info(const ghost_ctx *ctx, ghost_stats *out) {
   out->n_support_dofs = p.n_support;
   out->n_inside_dofs = p.n_inside;
   out->n_gamma = ctx->dev.n_gamma;
+  out->n_cell_chunks = (int64_t)p.inside_chunks.size();
   out->macro = ctx->dev.macro ? 1 : 0;
   const int K = p.k + 1;
   int64_t tang = 1;
@@ -552,6 +553,20 @@ int ghost_faces(const ghost_ctx *ctx, int axis, int32_t *out, int64_t cap) {
     out[4 * f + 2] = fc[3 * f + 2];
     out[4 * f + 3] = ctx->plan.face_colour[axis][f];
   }
+  return GHOST_OK;
+}
+
+int ghost_cell_chunks(const ghost_ctx *ctx, int64_t *out, int64_t cap) {
+  if (!ctx || !out) return fail(GHOST_EINVAL, "null context or output");
+  const ghost::Plan &p = ctx->plan;
+  const int64_t n = (int64_t)p.inside_chunks.size();
+  if (cap < n) return fail(GHOST_EINVAL, "capacity %lld < %lld chunks", (long long)cap, (long long)n);
+  for (int col = 0; col < 8; ++col)
+    for (int64_t i = p.inside_colour_begin[col]; i < p.inside_colour_begin[col + 1]; ++i) {
+      out[3 * i] = p.inside_chunks[i].base;
+      out[3 * i + 1] = p.inside_chunks[i].count;
+      out[3 * i + 2] = col;
+    }
   return GHOST_OK;
 }
 

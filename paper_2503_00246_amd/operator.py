@@ -261,6 +261,13 @@ class GhostOperator:
                                            runs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nr))
         return boxes, visits[:nv], runs[:nr]
 
+    def cell_chunks(self):
+        """Chunks of the interior Laplacian: (n, 3) int64 of (first node, cell count, colour)."""
+        n = self.stats["n_cell_chunks"]
+        out = np.zeros((max(n, 1), 3), dtype=np.int64)
+        L.check(self._lib.ghost_cell_chunks(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n))
+        return out[:n]
+
     def set_timing(self, on=True):
         """Record per-kernel HIP events in later applies / VJPs (see kernel_times)."""
         L.check(self._lib.ghost_set_timing(self._h, 1 if on else 0))

@@ -270,6 +270,47 @@ def test_generated_macro_coupling_reproduces_oracle():
         assert np.max(np.abs(g.T @ Hm @ g - ref)) <= 1e-12 * np.max(np.abs(ref)), k
 
 
+@pytest.mark.parametrize("d,k,n", [(2, 2, 24), (3, 1, 14), (3, 3, 14), (3, 5, 12), (3, 7, 40), (2, 7, 200)])
+def test_cell_chunks_cover_inside_cells_and_colours_share_no_node(d, k, n):
+    """The interior Laplacian's chunks (runs of inside cells along x, one launch per colour): every inside
+    cell of the oracle's classification lies in exactly one chunk, and no lattice node belongs to cells of
+    two different chunks of one colour (so a launch needs no atomics).  The last two meshes have runs of
+    inside cells longer than a chunk (16 cells at 3D k = 7, 128 at 2D k = 7), so that neighbouring chunks
+    of one run are checked too."""
+    centre = (0.011, 0.017, 0.023)[:d]
+    h = 2.0 / n
+    op = GhostOperator(d, (n,) * d, (-1.0,) * d, h, k, gamma_paper(k, h), centre=centre, radius=0.73, device=-1)
+    cls = omesh.classify_ball((n,) * d, (-1.0,) * d, h, centre, 0.73)
+    L = np.array([k * n + 1] * d, dtype=np.int64)
+    stride = np.cumprod(np.concatenate([[1], L[:-1]]))
+    chunks = op.cell_chunks()
+    assert len(chunks) == op.stats["n_cell_chunks"] > 0
+    first = (chunks[:, :1] // stride[None, :]) % L[None, :]          # first node multi-index per chunk
+    assert np.all(first % k == 0)
+    # every cell of every chunk, with its chunk id and colour
+    cid = np.repeat(np.arange(len(chunks)), chunks[:, 1])
+    step = np.arange(len(cid)) - np.repeat(np.cumsum(chunks[:, 1]) - chunks[:, 1], chunks[:, 1])
+    cells = first[cid] // k
+    cells[:, 0] += step
+    covered = np.zeros(cls.shape, dtype=np.int64)
+    np.add.at(covered, tuple(cells.T), 1)
+    assert np.array_equal(covered, (cls == omesh.INSIDE).astype(np.int64))
+    longest = max(int(c) for c in chunks[:, 1])
+    if n >= 40:
+        # some run is cut into several chunks
+        assert (cls == omesh.INSIDE).sum(axis=0).max() > longest
+    # nodes of each cell; within a colour, a node may belong to one chunk only
+    loc = np.stack(np.meshgrid(*[np.arange(k + 1)] * d, indexing="ij"), -1).reshape(-1, d)
+    nodes = ((k * cells[:, None, :] + loc[None, :, :]) * stride[None, None, :]).sum(-1)
+    col = np.repeat(chunks[cid, 2][:, None], len(loc), axis=1).ravel()
+    own = np.repeat(cid[:, None], len(loc), axis=1).ravel()
+    nodes = nodes.ravel()
+    order = np.lexsort((own, nodes, col))
+    col, nodes, own = col[order], nodes[order], own[order]
+    same = (col[1:] == col[:-1]) & (nodes[1:] == nodes[:-1])
+    assert not np.any(same & (own[1:] != own[:-1]))
+
+
 def test_bad_cell_class_value(lib):
     cls = (ctypes.c_byte * 64)(*([0] * 63 + [5]))
     rc, msg = _raw_setup(lib, kind=1, cls=ctypes.cast(cls, ctypes.POINTER(ctypes.c_byte)))
