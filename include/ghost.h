@@ -15,6 +15,10 @@
  * gamma_j carries every scalar of the paper's g_F; the paper's choice is
  * gamma_j = gamma_A h^{2j-1} / (j!)^2, gamma_A applied once.
  *
+ * Also: the macro-patch stabilisation in place of G (GHOST_MACRO_PATCH, §2.2), the Laplacian on the
+ * cells the boundary does not cut (ghost_cell_apply, §2.1), conjugate gradients on M + G (ghost_cg),
+ * and a single-face microbenchmark (ghost_face_bench, §3).
+ *
  * Vectors live on the full node lattice: L_a = k*n_a + 1 nodes per axis, node
  * multi-index I, linear index I_0 + L_0 I_1 + L_0 L_1 I_2 (x fastest, §2.4).
  * Entries outside the support (the union of all face patches) are neither read

@@ -311,6 +311,16 @@ def test_cell_chunks_cover_inside_cells_and_colours_share_no_node(d, k, n):
     assert not np.any(same & (own[1:] != own[:-1]))
 
 
+def test_cell_chunks_capacity_checked(lib):
+    w = WORKLOADS["disk2d_q2_32"]
+    op = GhostOperator.from_workload(w, device=-1)
+    n = op.stats["n_cell_chunks"]
+    out = np.zeros((n, 3), dtype=np.int64)
+    rc = lib.ghost_cell_chunks(op._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n - 1)
+    assert rc == L.GHOST_EINVAL and "capacity" in lib.ghost_last_error().decode()
+    assert lib.ghost_cell_chunks(op._h, None, n) == L.GHOST_EINVAL
+
+
 def test_bad_cell_class_value(lib):
     cls = (ctypes.c_byte * 64)(*([0] * 63 + [5]))
     rc, msg = _raw_setup(lib, kind=1, cls=ctypes.cast(cls, ctypes.POINTER(ctypes.c_byte)))
