@@ -50,3 +50,29 @@ def test_cell_apply_matches_oracle(d, k, n):
     ys = op.cell_apply(ut)
     op.apply(ut, ys, accumulate=True)
     assert nerr(ys.cpu().numpy(), ref + go.apply(u)) <= 1e-12
+
+
+# meshes whose rows of inside cells are longer than a chunk (64 cells at 3D k = 3, 28 at k = 5, 16 at
+# k = 7, 128 at 2D k = 7): neighbouring chunks of a row run in different launches, and every chunk
+# applies its even and its odd cells in two phases
+LONG_ROWS = [(3, 3, (96, 96, 96)), (3, 5, (48, 48, 48)), (3, 7, (40, 40, 40)), (2, 7, (200, 200))]
+
+
+@pytest.mark.parametrize("d,k,n", LONG_ROWS)
+def test_cell_apply_rows_longer_than_a_chunk(d, k, n):
+    from paper_2503_00246_amd.operator import GhostOperator
+    lo, h = (-1.0,) * d, 2.0 / n[0]
+    centre, radius = ((0.011, 0.017, 0.023) if d == 3 else (0.013, 0.021)), 0.73
+    cls = mesh.classify_ball(n, lo, h, centre, radius)
+    op = GhostOperator(d, n, lo, h, k, gamma_paper(k, h), centre=centre, radius=radius)
+    chunks = op.cell_chunks()
+    longest_row = int((cls == mesh.INSIDE).sum(axis=0).max())
+    assert longest_row > int(chunks[:, 1].max())  # some row is cut into several chunks
+    co = CellOracle(d, n, lo, h, k, cls)
+    u = uniform_vector(co.n_lattice, SEED_U)
+    ref = co.apply(u)
+    y = op.cell_apply(torch.from_numpy(u).cuda()).cpu().numpy()
+    assert nerr(y, ref) <= 1e-12
+    u32 = u.astype(np.float32)
+    y32 = op.cell_apply(torch.from_numpy(u32).cuda()).cpu().numpy().astype(np.float64)
+    assert nerr(y32, co.apply(u32.astype(np.float64))) <= 1e-5
