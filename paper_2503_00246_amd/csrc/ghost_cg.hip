@@ -204,7 +204,7 @@ __global__ void cast_kernel(const Run *segs, int n_segs, const double *a, float 
 }
 
 // mode 0: scal[RR] = s; 1: scal[PQ] = s, scal[ALPHA] = scal[RR] / s;
-// 2: scal[BETA] = s / scal[RR], scal[RR] = s; 3: scal[TMP] = s
+// 2: scal[BETA] = s / scal[RR], scal[RR] = s; 3: scal[TMP] = s  (a zero denominator gives 0)
 // (the partial sums of two arrays: n of `partial` and n2 of `partial2`)
 __global__ void reduce_kernel(const double *partial, int n, const double *partial2, int n2, double *scal, int mode) {
   __shared__ double red[kBlockThreads];
@@ -223,10 +223,12 @@ __global__ void reduce_kernel(const double *partial, int n, const double *partia
     if (mode == 0) {
       scal[S_RR] = v;
     } else if (mode == 1) {
+      // a step after exact convergence has p = 0: alpha = 0 keeps x and r instead of 0 / 0
       scal[S_PQ] = v;
-      scal[S_ALPHA] = scal[S_RR] / v;
+      scal[S_ALPHA] = v != 0.0 ? scal[S_RR] / v : 0.0;
     } else if (mode == 2) {
-      scal[S_BETA] = v / scal[S_RR];
+      const double rr = scal[S_RR];
+      scal[S_BETA] = rr != 0.0 ? v / rr : 0.0;
       scal[S_RR] = v;
     } else {
       scal[S_TMP] = v;
