@@ -86,3 +86,16 @@ class CellOracle:
         dofs = cell_dofs(self.cells, self.k, self.L)
         np.add.at(y, dofs, u[dofs] @ self.K.T)
         return y
+
+    def apply_at(self, u, nodes):
+        """Entries of the apply at the given lattice nodes, from the inside cells that contain them only."""
+        nodes = np.asarray(nodes, dtype=np.int64)
+        if self.K is None:
+            return np.zeros(len(nodes))
+        dofs = cell_dofs(self.cells, self.k, self.L)
+        mark = np.zeros(self.n_lattice, dtype=bool)
+        mark[nodes] = True
+        sel = mark[dofs].any(axis=1)
+        y = np.zeros(self.n_lattice)
+        np.add.at(y, dofs[sel], u[dofs[sel]] @ self.K.T)
+        return y[nodes]

@@ -76,3 +76,27 @@ def test_cell_apply_rows_longer_than_a_chunk(d, k, n):
     u32 = u.astype(np.float32)
     y32 = op.cell_apply(torch.from_numpy(u32).cuda()).cpu().numpy().astype(np.float64)
     assert nerr(y32, co.apply(u32.astype(np.float64))) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cell_apply_full_size_sampled(precision):
+    """128^3 Q5 in the benchmark's configuration: y at every node of 2,000 seeded inside cells against the
+    oracle summing all inside cells that contain those nodes."""
+    from oracle.cell import cell_dofs
+    from paper_2503_00246_amd.operator import GhostOperator
+    from paper_2503_00246_amd.workloads import WORKLOADS
+    w = WORKLOADS["ball3d_q5_128"]
+    cls = mesh.classify_ball(w.n, w.lo, w.h, w.centre, w.radius)
+    co = CellOracle(w.d, w.n, w.lo, w.h, w.k, cls)
+    op = GhostOperator.from_workload(w)
+    pick = np.random.default_rng(7).choice(len(co.cells), 2000, replace=False)
+    nodes = np.unique(cell_dofs(co.cells[pick], w.k, co.L))
+    u = uniform_vector(co.n_lattice, SEED_U)
+    idx = torch.from_numpy(nodes).cuda()
+    if precision == "fp64":
+        y = op.cell_apply(torch.from_numpy(u).cuda())[idx].cpu().numpy()
+        assert nerr(y, co.apply_at(u, nodes)) <= 1e-12
+    else:
+        u32 = u.astype(np.float32)
+        y = op.cell_apply(torch.from_numpy(u32).cuda())[idx].cpu().numpy().astype(np.float64)
+        assert nerr(y, co.apply_at(u32.astype(np.float64), nodes)) <= 1e-5

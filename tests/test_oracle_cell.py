@@ -53,3 +53,15 @@ def test_interior_operator_energy_and_constants():
     for axis in range(3):
         u = coords[:, axis]
         assert abs(u @ o.apply(u) - len(o.cells) * h ** 3) <= 1e-11 * len(o.cells) * h ** 3
+
+
+def test_apply_at_matches_apply():
+    """apply_at sums the same cells as apply at the sampled nodes."""
+    d, k, n = 3, 2, (9, 8, 7)
+    lo, h = (-1.0,) * 3, 2.0 / 9
+    cls = mesh.classify_ball(n, lo, h, (0.011, 0.017, 0.023), 0.73)
+    co = cell.CellOracle(d, n, lo, h, k, cls)
+    u = np.random.default_rng(3).uniform(-1, 1, co.n_lattice)
+    y = co.apply(u)
+    nodes = np.random.default_rng(4).choice(co.n_lattice, 300, replace=False)
+    np.testing.assert_allclose(co.apply_at(u, nodes), y[nodes], rtol=0, atol=1e-14 * np.max(np.abs(y)))
