@@ -211,3 +211,37 @@ def test_macro_rejections():
     with pytest.raises(L.GhostError) as e:
         op.face_bench(inp)
     assert e.value.code == L.GHOST_ESTATE
+
+
+def test_macro_vjp_finite_differences_full_mesh():
+    """96^3 Q4: central differences of L = 0.5 |S u - t|^2 in u (3 seeded directions, step 1e-6) and in
+    gamma_M (relative step 1e-6), formed as sum (y+ - y-)(y+ + y- - 2t)/2 to avoid cancellation; adjoint
+    identity <w, S u> = <S w, u>."""
+    from paper_2503_00246_amd.workloads import SEED_FD
+    w = WORKLOADS["ball3d_q4_96"]
+    op = gpu_op(w)
+    u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda()
+    t = torch.from_numpy(uniform_vector(w.n_lattice, SEED_T)).cuda()
+    y = op.apply(u)
+    du, dg = op.vjp(u, y - t)
+
+    def dL(yp, ym, step):
+        return float(((yp - ym) * (yp + ym - 2 * t)).sum()) / 2 / (2 * step)
+
+    rng = np.random.default_rng(SEED_FD)
+    for _ in range(3):
+        v = torch.from_numpy(rng.uniform(-1, 1, w.n_lattice)).cuda()
+        eps = 1e-6
+        fd = dL(op.apply(u + eps * v), op.apply(u - eps * v), eps)
+        an = float(du @ v)
+        assert abs(fd - an) <= 1e-6 * abs(an)
+    step = 1e-6 * GAMMA_MACRO
+    op.set_gamma([GAMMA_MACRO + step])
+    yp = op.apply(u)
+    op.set_gamma([GAMMA_MACRO - step])
+    ym = op.apply(u)
+    op.set_gamma([GAMMA_MACRO])
+    assert abs(dL(yp, ym, step) - float(dg[0])) <= 1e-6 * abs(float(dg[0]))
+    wv = torch.from_numpy(uniform_vector(w.n_lattice, 21)).cuda()
+    a_, b_ = float(wv @ op.apply(u)), float(op.apply(wv) @ u)
+    assert abs(a_ - b_) <= 1e-12 * abs(a_)
