@@ -318,3 +318,37 @@ def test_multiball_full_size_on_face_subset():
     ref = o.apply_at(u, dofs)
     y = op.apply(torch.from_numpy(u).cuda())[torch.from_numpy(dofs).cuda()].cpu().numpy()
     assert nerr(y, ref) <= TOL64
+
+
+def test_argument_errors_are_reported_before_any_launch():
+    """Null and overlapping vectors are refused with GHOST_EINVAL by the C ABI (checked on the host, before
+    any kernel runs); the binding refuses tensors of the wrong type, device or size."""
+    import ctypes
+    from paper_2503_00246_amd import _lib as L
+    w = WORKLOADS["disk2d_q2_32"]
+    op = gpu_op(w)
+    lib = op._lib
+    u = torch.zeros(w.n_lattice, dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(u)
+    pu, py = ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(y.data_ptr())
+    shifted = ctypes.c_void_p(u.data_ptr() + 8)
+    dg = torch.zeros(w.k, dtype=torch.float64, device="cuda")
+    pdg = ctypes.c_void_p(dg.data_ptr())
+    cases = [
+        lib.ghost_apply(op._h, None, py, 0, None),
+        lib.ghost_apply(op._h, pu, None, 0, None),
+        lib.ghost_apply(op._h, pu, pu, 0, None),
+        lib.ghost_apply(op._h, pu, shifted, 1, None),
+        lib.ghost_apply_f32(op._h, pu, pu, 0, None),
+        lib.ghost_cell_apply(op._h, pu, shifted, None),
+        lib.ghost_vjp(op._h, pu, py, pu, pdg, 0, None),
+        lib.ghost_vjp(op._h, pu, py, py, None, 0, None),
+    ]
+    assert all(rc == L.GHOST_EINVAL for rc in cases), cases
+    torch.cuda.synchronize()
+    with pytest.raises(TypeError):
+        op.apply(u.float())
+    with pytest.raises(ValueError):
+        op.apply(u[:-1])
+    with pytest.raises(ValueError):
+        op.apply(u.cpu())
