@@ -352,3 +352,27 @@ def test_argument_errors_are_reported_before_any_launch():
         op.apply(u[:-1])
     with pytest.raises(ValueError):
         op.apply(u.cpu())
+
+
+def test_calls_run_on_the_current_stream():
+    """Inside a torch side stream (default priority) the apply, the VJP and the interior Laplacian are
+    enqueued on that stream and give the default stream's results."""
+    w = WORKLOADS["ball3d_q3_64"]
+    op = gpu_op(w)
+    u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda()
+    ref_y = op.apply(u)
+    ref_du, ref_dg = op.vjp(u, ref_y)
+    ref_c = op.cell_apply(u)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        y = op.apply(u)
+        du, dg = op.vjp(u, y)
+        c = op.cell_apply(u)
+    side.synchronize()
+    scale = float(ref_y.abs().max())
+    assert float((y - ref_y).abs().max()) <= 1e-14 * scale
+    assert float((du - ref_du).abs().max()) <= 1e-13 * float(ref_du.abs().max())
+    assert float((dg - ref_dg).abs().max()) <= 1e-13 * float(ref_dg.abs().max())
+    assert float((c - ref_c).abs().max()) <= 1e-14 * float(ref_c.abs().max())
