@@ -376,3 +376,39 @@ def test_calls_run_on_the_current_stream():
     assert float((du - ref_du).abs().max()) <= 1e-13 * float(ref_du.abs().max())
     assert float((dg - ref_dg).abs().max()) <= 1e-13 * float(ref_dg.abs().max())
     assert float((c - ref_c).abs().max()) <= 1e-14 * float(ref_c.abs().max())
+
+
+def test_vjp_and_cell_graph_replay():
+    """A VJP (du overwritten, dgamma reduced) and an interior-Laplacian apply captured in one HIP graph,
+    replayed three times with eager resets and synchronisation between replays, each replay checked
+    against the eager results."""
+    w = WORKLOADS["ball3d_q3_64"]
+    op = gpu_op(w)
+    u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda()
+    wv = torch.from_numpy(uniform_vector(w.n_lattice, 21)).cuda()
+    ref_du, ref_dg = op.vjp(u, wv)
+    ref_c = op.cell_apply(u)
+    du = torch.zeros_like(u)
+    yc = torch.zeros_like(u)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream
+        op.vjp(u, wv, du=du)
+        op.cell_apply(u, yc)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        _, dg = op.vjp(u, wv, du=du, accumulate=False)
+        op.cell_apply(u, yc)
+    for _ in range(3):
+        du.fill_(5.0)
+        yc.zero_()
+        dg.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        sup = ref_du != 0
+        assert float((du[sup] - ref_du[sup]).abs().max()) <= 1e-13 * float(ref_du.abs().max())
+        assert float((dg - ref_dg).abs().max()) <= 1e-13 * float(ref_dg.abs().max())
+        assert float((yc - ref_c).abs().max()) <= 1e-14 * float(ref_c.abs().max())
