@@ -412,3 +412,26 @@ def test_vjp_and_cell_graph_replay():
         assert float((du[sup] - ref_du[sup]).abs().max()) <= 1e-13 * float(ref_du.abs().max())
         assert float((dg - ref_dg).abs().max()) <= 1e-13 * float(ref_dg.abs().max())
         assert float((yc - ref_c).abs().max()) <= 1e-14 * float(ref_c.abs().max())
+
+
+def test_destroy_returns_device_memory():
+    """ghost_destroy frees every device allocation of a context (plan, tables, box layout, VJP and CG
+    workspaces): free device memory is back where it started after repeated set-up, use and destroy."""
+    from paper_2503_00246_amd.operator import GhostOperator
+    w = WORKLOADS["ball3d_q3_64"]
+    u = torch.from_numpy(uniform_vector(w.n_lattice, SEED_U)).cuda()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for i in range(6):
+        op = GhostOperator.from_workload(w)
+        y = op.apply(u)
+        op.vjp(u, y)
+        if i % 2 == 0:
+            op.cg(torch.where(op.mass_diag() > 0, u, torch.zeros_like(u)), max_iter=3)
+        torch.cuda.synchronize()
+        op.close()
+        del op, y
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert free1 >= free0 - 64 * 2 ** 20, (free0, free1)
